@@ -1,0 +1,214 @@
+/*
+ * wmd.h -- C ABI of libwmd: sparse Sinkhorn-Knopp Word Mover's Distance of
+ * one query document against many target documents, on an AMD MI355X
+ * (gfx950) GPU.
+ *
+ * What is computed (Algorithm 1 of Tithi & Petrini, "An Efficient
+ * Shared-memory Parallel Sinkhorn-Knopp Algorithm to Compute the Word
+ * Mover's Distance", in the sparse form of its Sec. 4):
+ *
+ *   r      query histogram over its v_r words with positive weight, sum 1
+ *   c_j    histogram of target document j, sum 1
+ *   M      v_r x V Euclidean distances between query words and vocabulary
+ *          words (Sec. 2), computed only for the query rows
+ *   K      exp(-lambda M)
+ *   x      v_r x N, starts at 1/v_r; repeated `iters` times:
+ *            u = 1/x;  v = c .* (1 ./ (K^T u))   [only where c != 0: SDDMM]
+ *            x = diag(1/r) K v                   [SpMM]
+ *   final  u = 1/x;  v = c .* (1 ./ (K^T u));
+ *          WMD_j = sum_k u_kj ((K .* M) v)_kj = <P_j, M>, P_j = diag(u_j) K diag(v_j)
+ *          (Eq. 1; no entropy term)
+ *
+ * Conventions for every entry point:
+ *  - Status: 0 (WMD_OK) on success, a negative WMD_E* code on failure; then
+ *    wmd_last_error() returns a message for the calling thread and no output
+ *    argument has been written.
+ *  - Host pointers are read during the call only; the caller keeps ownership.
+ *  - Device pointers are HIP device addresses on the corpus's device.
+ *  - Streams are hipStream_t values passed as void* (NULL = null stream).
+ *  - Nothing here allocates or frees caller memory.
+ */
+#ifndef WMD_H
+#define WMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WMD_OK         0
+#define WMD_EINVAL    (-1)  /* invalid argument or input data */
+#define WMD_ENOMEM    (-2)  /* device (or pinned host) allocation failed */
+#define WMD_EDEVICE   (-3)  /* a HIP runtime call failed */
+#define WMD_ETIMEDOUT (-4)  /* wmd_server_wait timed out; the ticket stays valid */
+#define WMD_ESHUTDOWN (-5)  /* the server is shutting down */
+#define WMD_ENOTFOUND (-6)  /* unknown or already collected server ticket */
+
+#define WMD_DIST_FP32 0     /* distance GEMM in FP32 (MFMA 16x16x4 f32) */
+#define WMD_DIST_BF16 1     /* distance GEMM in BF16 with FP32 accumulation */
+
+typedef struct wmd_corpus wmd_corpus;
+
+typedef struct wmd_corpus_options {
+    int32_t device;   /* HIP device ordinal; -1 = the calling thread's current device */
+    int32_t bf16;     /* nonzero: also keep BF16 copies of the corpus's embedding rows,
+                         required by WMD_DIST_BF16 queries */
+} wmd_corpus_options;
+
+typedef struct wmd_query_options {
+    int32_t precision;        /* WMD_DIST_FP32 (default) or WMD_DIST_BF16 */
+    float   recompute_below;  /* distances below this value are recomputed as a direct
+                                 FP32 sum of squared differences (the expansion
+                                 |a|^2 + |b|^2 - 2 a.b cancels there); < 0 selects the
+                                 default: 0.5 for FP32, 1e-2 for BF16 */
+    int32_t log_domain;       /* nonzero: divide each vocabulary column of K by its
+                                 largest entry exp(-lambda min_k M[k, i]); the
+                                 iterates x, u and the result are unchanged in exact
+                                 arithmetic, and K cannot underflow for large lambda */
+    int32_t iters_per_launch; /* 0: all iterations and the final step in one fused
+                                 launch; k > 0: at most k iterations per launch, x kept
+                                 in device memory between launches */
+} wmd_query_options;
+
+typedef struct wmd_corpus_info {
+    int64_t V, N, nnz;        /* vocabulary size, documents, nonzeros after dropping
+                                 zero weights */
+    int64_t U;                /* distinct vocabulary words used by the documents */
+    int32_t dim;              /* embedding dimension */
+    int32_t max_doc_words;    /* largest document (distinct words) */
+    int32_t device;           /* HIP device ordinal holding the corpus */
+    int32_t has_bf16;
+    int64_t device_bytes;     /* device memory held by the corpus itself */
+} wmd_corpus_info;
+
+/* Fill *opt with the defaults (device -1, no BF16 copies). */
+void wmd_corpus_options_init(wmd_corpus_options* opt);
+
+/* Fill *opt with the defaults (FP32, recompute_below -1, no log domain,
+ * fused launch). */
+void wmd_query_options_init(wmd_query_options* opt);
+
+/*
+ * Upload a vocabulary embedding table and a bag-of-words corpus (Sec. 4,
+ * "A Python Implementation" and "Dataset": vecs is V x dim, c is V x N
+ * sparse with normalised columns).
+ *
+ *  vecs      host, V*dim floats, row-major: row i is the embedding of word i
+ *  doc_ptr   host, N+1 int64, CSR by document (the transpose of the paper's
+ *            V x N c): document j holds entries doc_ptr[j] .. doc_ptr[j+1]-1;
+ *            doc_ptr[0] == 0, non-decreasing
+ *  word_ids  host, doc_ptr[N] int32 vocabulary ids in [0, V), distinct within
+ *            a document
+ *  weights   host, doc_ptr[N] floats >= 0 (raw counts or frequencies); the
+ *            library drops zeros and normalises each document to sum 1
+ *  opt       nullable
+ *  out       receives the corpus handle (untouched on error)
+ *
+ * Errors: WMD_EINVAL for V <= 0, dim <= 0, N <= 0, a bad doc_ptr, an id out
+ * of range, a repeated id within a document, a negative or non-finite
+ * weight, a document with no positive weight, more than 2^31-1 nonzeros;
+ * WMD_ENOMEM, WMD_EDEVICE.
+ */
+int wmd_corpus_create(const float* vecs, int64_t V, int32_t dim,
+                      const int64_t* doc_ptr, const int32_t* word_ids,
+                      const float* weights, int64_t N,
+                      const wmd_corpus_options* opt, wmd_corpus** out);
+
+/* Release every device and host resource of the corpus after waiting for its
+ * outstanding work.  NULL is a no-op.  The handle must not be in use by
+ * another thread or by a server. */
+void wmd_corpus_destroy(wmd_corpus* corpus);
+
+/* Sizes and resources of a corpus. */
+int wmd_corpus_info_get(const wmd_corpus* corpus, wmd_corpus_info* out);
+
+/*
+ * Distances from one query to every document (Algorithm 1; lazily computed
+ * M rows, Sec. 4), synchronous.
+ *
+ *  qids, qweights  host, n entries; query word ids in [0, V), distinct, and
+ *                  weights >= 0 (zeros dropped: I = (r > 0); the rest are
+ *                  normalised to sum 1)
+ *  lambda          >= 0, finite; K = exp(-lambda M)
+ *  iters           >= 0 x-updates; the final u/v/WMD step always runs once
+ *  out_dist        host, N doubles: out_dist[j] = WMD to document j (input
+ *                  order)
+ *  out_resid       host, N doubles or NULL: sum_k |(P_j 1)_k - r_k|, the row
+ *                  marginal residual of the final plan, accumulated in FP64
+ *
+ * Errors: WMD_EINVAL (no positive weight, id out of range or repeated,
+ * lambda < 0 or not finite, iters < 0, BF16 without BF16 copies),
+ * WMD_ENOMEM, WMD_EDEVICE.  Thread-safe: calls on one corpus are serialised.
+ */
+int wmd_query(wmd_corpus* corpus, const int32_t* qids, const float* qweights,
+              int32_t n, float lambda, int32_t iters,
+              const wmd_query_options* opt, double* out_dist, double* out_resid);
+
+/*
+ * Same computation, stream-ordered: the query arrays are host memory (read
+ * before return), the outputs are DEVICE pointers to N doubles (dev_resid
+ * nullable), written in stream order on `stream`.  The call returns after
+ * enqueueing; argument errors are reported synchronously, device faults at
+ * the caller's next synchronisation.  Calls on one corpus share its
+ * workspace and are ordered after each other even across streams.
+ */
+int wmd_query_async(wmd_corpus* corpus, const int32_t* qids, const float* qweights,
+                    int32_t n, float lambda, int32_t iters,
+                    const wmd_query_options* opt, double* dev_dist,
+                    double* dev_resid, void* stream);
+
+/*
+ * B queries against the corpus in one distance-GEMM launch and one fused
+ * Sinkhorn launch per shape class (the paper's one-to-many evaluation, Sec. 3,
+ * applied to many queries at once).
+ *
+ *  q_ptr     host, B+1 int64: query b holds entries q_ptr[b] .. q_ptr[b+1]-1
+ *  qids, qweights  host, q_ptr[B] entries, as in wmd_query per query
+ *  lambdas, iters  host, B entries each (per-query lambda and iteration count)
+ *  out_dist  host, B*N doubles, row b = distances of query b
+ *  out_resid host, B*N doubles or NULL
+ *
+ * Results are bitwise identical to B separate wmd_query calls with the same
+ * options.  Errors as wmd_query, for any query of the batch.
+ */
+int wmd_query_batch(wmd_corpus* corpus, int32_t B, const int64_t* q_ptr,
+                    const int32_t* qids, const float* qweights,
+                    const float* lambdas, const int32_t* iters,
+                    const wmd_query_options* opt, double* out_dist,
+                    double* out_resid);
+
+/* Stream-ordered wmd_query_batch: outputs are DEVICE pointers (B*N doubles). */
+int wmd_query_batch_async(wmd_corpus* corpus, int32_t B, const int64_t* q_ptr,
+                          const int32_t* qids, const float* qweights,
+                          const float* lambdas, const int32_t* iters,
+                          const wmd_query_options* opt, double* dev_dist,
+                          double* dev_resid, void* stream);
+
+/*
+ * Kernel timing, recorded with HIP events on the stream the kernels run on,
+ * for every query or batch call made while timing is enabled.
+ * wmd_set_timing(corpus, 1) enables it and clears the totals; 0 disables it.
+ * wmd_timing_get waits for the recorded events and returns milliseconds.
+ */
+typedef struct wmd_timing {
+    int64_t calls;            /* timed calls since timing was enabled */
+    double dist_ms;           /* distance GEMM + epilogue, summed over the calls */
+    double sinkhorn_ms;       /* Sinkhorn iterations + final WMD step, summed */
+    float last_dist_ms;       /* the most recent timed call */
+    float last_sinkhorn_ms;
+    int32_t launches;         /* kernel launches of the most recent call */
+} wmd_timing;
+
+int wmd_set_timing(wmd_corpus* corpus, int32_t enable);
+int wmd_timing_get(wmd_corpus* corpus, wmd_timing* out);
+
+/* Message describing the last non-zero status returned to this thread. */
+const char* wmd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WMD_H */

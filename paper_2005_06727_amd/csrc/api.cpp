@@ -1,0 +1,699 @@
+// Host runtime of libwmd: argument validation, corpus upload, per-corpus
+// workspace, query planning and kernel launches.  Every entry point declared
+// in include/wmd.h except the server lives here.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "wmd_corpus.h"
+
+namespace wmd {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(e == hipErrorOutOfMemory ? WMD_ENOMEM : WMD_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+DeviceGuard::DeviceGuard(int dev) : dev_(dev) {
+    if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
+    ok_ = (prev_ == dev_) || hipSetDevice(dev_) == hipSuccess;
+}
+DeviceGuard::~DeviceGuard() {
+    if (prev_ >= 0 && prev_ != dev_) (void)hipSetDevice(prev_);
+}
+
+namespace {
+
+template <typename T>
+hipError_t dalloc(T** p, size_t count) {
+    return hipMalloc(reinterpret_cast<void**>(p), std::max<size_t>(count, 1) * sizeof(T));
+}
+
+template <typename T>
+void dfree(T*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+template <typename T>
+void hfree(T*& p) {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+// ---------------------------------------------------------------- queries
+
+int plan_query(const wmd_corpus* c, const int32_t* qids, const float* qw, int32_t n, float lambda,
+               int32_t iters, int bf16, PlannedQuery* out) {
+    if (n <= 0 || !qids || !qw) return fail(WMD_EINVAL, "query: empty or null word arrays");
+    if (!std::isfinite(lambda) || lambda < 0.f) return fail(WMD_EINVAL, "query: lambda must be finite and >= 0");
+    if (iters < 0) return fail(WMD_EINVAL, "query: iters must be >= 0");
+    if (bf16 && !c->dc.act_bf16) return fail(WMD_EINVAL, "query: BF16 distances need a corpus created with bf16 copies");
+    std::vector<int32_t> sorted(qids, qids + n);
+    std::sort(sorted.begin(), sorted.end());
+    for (int32_t k = 0; k < n; ++k) {
+        if (sorted[k] < 0 || sorted[k] >= c->dc.V) return fail(WMD_EINVAL, "query: word id %d out of range", sorted[k]);
+        if (k > 0 && sorted[k] == sorted[k - 1]) return fail(WMD_EINVAL, "query: word id %d repeated", sorted[k]);
+    }
+    out->ids.clear();
+    std::vector<double> w;
+    double total = 0.0;
+    for (int32_t k = 0; k < n; ++k) {
+        const float wk = qw[k];
+        if (!std::isfinite(wk) || wk < 0.f) return fail(WMD_EINVAL, "query: weight %d is negative or not finite", k);
+        if (wk > 0.f) {   // I = (r > 0)
+            out->ids.push_back(qids[k]);
+            w.push_back((double)wk);
+            total += (double)wk;
+        }
+    }
+    const int m = (int)out->ids.size();
+    if (m == 0) return fail(WMD_EINVAL, "query: no word with positive weight");
+    if (m > kMaxQueryWords) return fail(WMD_EINVAL, "query: %d words exceed the limit of %d", m, kMaxQueryWords);
+    out->r.resize(m);
+    out->rinv.resize(m);
+    for (int k = 0; k < m; ++k) {
+        out->r[k] = (float)(w[k] / total);
+        out->rinv[k] = (float)(total / w[k]);
+    }
+    out->m = m;
+    out->ldk = (int)align_up((size_t)m, 4);
+    out->lambda = lambda;
+    out->iters = iters;
+    return WMD_OK;
+}
+
+static int ensure_workspace(wmd_corpus* c, size_t kfloats, size_t xfloats, size_t pbytes, size_t obytes,
+                            bool need_host_out) {
+    Workspace& w = c->ws;
+    const bool grow = kfloats > w.kcap || xfloats > w.xcap || pbytes > w.pcap || obytes > w.ocap ||
+                      (need_host_out && obytes > w.hocap);
+    if (!grow) return WMD_OK;
+    // nothing queued may still use the old buffers
+    if (c->done_valid) {
+        hipError_t e = hipEventSynchronize(c->done);
+        if (e != hipSuccess) return hip_fail(e, "workspace: wait for previous work");
+    }
+    if (c->staging_valid) (void)hipEventSynchronize(c->staging_free);
+    hipError_t e = hipSuccess;
+    auto grown = [](size_t need) { return need + need / 4; };
+    if (kfloats > w.kcap) {
+        dfree(w.Kt);
+        dfree(w.KMt);
+        w.kcap = 0;
+        size_t cap = grown(kfloats);
+        if ((e = dalloc(&w.Kt, cap)) != hipSuccess || (e = dalloc(&w.KMt, cap)) != hipSuccess)
+            return hip_fail(e, "workspace: K buffers");
+        w.kcap = cap;
+    }
+    if (xfloats > w.xcap) {
+        dfree(w.x);
+        w.xcap = 0;
+        size_t cap = grown(xfloats);
+        if ((e = dalloc(&w.x, cap)) != hipSuccess) return hip_fail(e, "workspace: x buffer");
+        w.xcap = cap;
+    }
+    if (pbytes > w.pcap) {
+        dfree(w.params);
+        hfree(w.h_params);
+        w.pcap = 0;
+        size_t cap = grown(pbytes);
+        if ((e = dalloc(&w.params, cap)) != hipSuccess) return hip_fail(e, "workspace: query parameters");
+        if ((e = hipHostMalloc(reinterpret_cast<void**>(&w.h_params), cap, hipHostMallocDefault)) != hipSuccess)
+            return hip_fail(e, "workspace: pinned staging");
+        w.pcap = cap;
+        c->staging_valid = false;
+    }
+    if (obytes > w.ocap) {
+        dfree(w.out);
+        w.ocap = 0;
+        size_t cap = grown(obytes);
+        if ((e = dalloc(reinterpret_cast<char**>(&w.out), cap)) != hipSuccess)
+            return hip_fail(e, "workspace: output buffer");
+        w.ocap = cap;
+    }
+    if (need_host_out && obytes > w.hocap) {
+        hfree(w.h_out);
+        w.hocap = 0;
+        size_t cap = grown(obytes);
+        if ((e = hipHostMalloc(reinterpret_cast<void**>(&w.h_out), cap, hipHostMallocDefault)) != hipSuccess)
+            return hip_fail(e, "workspace: pinned output");
+        w.hocap = cap;
+    }
+    return WMD_OK;
+}
+
+// Wait for a timed call's events and add its kernel times to the totals.
+int fold_timing_slot(wmd_corpus* c, int slot) {
+    hipError_t e;
+    float d = 0.f, k = 0.f;
+    if ((e = hipEventSynchronize(c->ev[slot][2])) != hipSuccess) return hip_fail(e, "timing: wait");
+    if ((e = hipEventElapsedTime(&d, c->ev[slot][0], c->ev[slot][1])) != hipSuccess ||
+        (e = hipEventElapsedTime(&k, c->ev[slot][1], c->ev[slot][2])) != hipSuccess)
+        return hip_fail(e, "timing: elapsed");
+    c->slot_pending[slot] = false;
+    c->timed_calls += 1;
+    c->dist_ms_total += d;
+    c->sink_ms_total += k;
+    if (slot == c->last_slot) {
+        c->last_dist_ms = d;
+        c->last_sink_ms = k;
+    }
+    return WMD_OK;
+}
+
+// Enqueue K1 + the fused Sinkhorn launches for `qs` on `stream`.  Row b of
+// dev_out (and dev_res when non-null) receives query b's N results.
+int run_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_query_options& opt,
+                double* dev_out, double* dev_res, hipStream_t stream, bool need_host_out) {
+    const DevCorpus& dc = c->dc;
+    const int B = (int)qs.size();
+    const int64_t N = dc.N, U = dc.U;
+    size_t sum_ldk = 0, sum_m = 0;
+    int max_iters = 0, max_m = 0;
+    for (const auto& q : qs) {
+        sum_ldk += q.ldk;
+        sum_m += q.m;
+        max_iters = std::max(max_iters, q.iters);
+        max_m = std::max(max_m, q.m);
+    }
+    const int per_launch = opt.iters_per_launch > 0 ? opt.iters_per_launch : INT_MAX;
+    const bool chunked = per_launch < max_iters;
+    const size_t kfloats = (size_t)U * sum_ldk;
+    const size_t xfloats = chunked ? (size_t)N * sum_ldk : 0;
+    // parameter block: QueryDev[B] | qlist[B] | qid[sum_m] | r[sum_m] | rinv[sum_m]
+    const size_t off_ql = align_up(sizeof(QueryDev) * B, 256);
+    const size_t off_id = align_up(off_ql + sizeof(int32_t) * B, 256);
+    const size_t off_r = align_up(off_id + sizeof(int32_t) * sum_m, 256);
+    const size_t off_ri = align_up(off_r + sizeof(float) * sum_m, 256);
+    const size_t pbytes = align_up(off_ri + sizeof(float) * sum_m, 256);
+    const size_t obytes = need_host_out ? sizeof(double) * (size_t)B * N * (dev_res ? 2 : 1) : 0;
+    int rc = ensure_workspace(c, kfloats, xfloats, pbytes, obytes, need_host_out);
+    if (rc) return rc;
+    Workspace& w = c->ws;
+    if (need_host_out) {
+        dev_out = w.out;
+        if (dev_res) dev_res = w.out + (size_t)B * N;
+    }
+
+    if (c->staging_valid) {
+        hipError_t e = hipEventSynchronize(c->staging_free);
+        if (e != hipSuccess) return hip_fail(e, "query: wait for staging area");
+    }
+    char* hp = w.h_params;
+    char* dp = w.params;
+    QueryDev* hq = reinterpret_cast<QueryDev*>(hp);
+    int32_t* hql = reinterpret_cast<int32_t*>(hp + off_ql);
+    int32_t* hid = reinterpret_cast<int32_t*>(hp + off_id);
+    float* hr = reinterpret_cast<float*>(hp + off_r);
+    float* hri = reinterpret_cast<float*>(hp + off_ri);
+    const float tau = opt.recompute_below >= 0.f ? opt.recompute_below
+                                                 : (opt.precision == WMD_DIST_BF16 ? 1e-2f : 0.5f);
+    size_t ko = 0, mo = 0;
+    for (int b = 0; b < B; ++b) {
+        const PlannedQuery& q = qs[b];
+        QueryDev& d = hq[b];
+        d.qid = reinterpret_cast<const int32_t*>(dp + off_id) + mo;
+        d.r = reinterpret_cast<const float*>(dp + off_r) + mo;
+        d.rinv = reinterpret_cast<const float*>(dp + off_ri) + mo;
+        d.Kt = w.Kt + (size_t)U * ko;
+        d.KMt = w.KMt + (size_t)U * ko;
+        d.x = chunked ? w.x + (size_t)N * ko : nullptr;
+        d.out = dev_out + (size_t)b * N;
+        d.resid = dev_res ? dev_res + (size_t)b * N : nullptr;
+        d.lambda = q.lambda;
+        d.tau2 = tau * tau;
+        d.m = q.m;
+        d.ldk = q.ldk;
+        d.iters = q.iters;
+        d.shift = opt.log_domain ? 1 : 0;
+        std::memcpy(hid + mo, q.ids.data(), sizeof(int32_t) * q.m);
+        std::memcpy(hr + mo, q.r.data(), sizeof(float) * q.m);
+        std::memcpy(hri + mo, q.rinv.data(), sizeof(float) * q.m);
+        ko += q.ldk;
+        mo += q.m;
+    }
+    // group queries by Sinkhorn launch shape: streaming-only first, then each register shape
+    std::vector<int> shape_of(B);
+    const int nshape = 8;
+    std::vector<int> cnt(nshape + 1, 0);
+    for (int b = 0; b < B; ++b) {
+        shape_of[b] = sinkhorn_shape_for(qs[b].m, kTileMaxDoc);
+        cnt[shape_of[b] + 1]++;
+    }
+    std::vector<int> start(nshape + 2, 0);
+    for (int s = 0; s <= nshape; ++s) start[s + 1] = start[s] + cnt[s];
+    {
+        std::vector<int> fill(start.begin(), start.end() - 1);
+        for (int b = 0; b < B; ++b) hql[fill[shape_of[b] + 1]++] = b;
+    }
+
+    hipError_t e;
+    if (c->done_valid && (e = hipStreamWaitEvent(stream, c->done, 0)) != hipSuccess)
+        return hip_fail(e, "query: order after previous call");
+    if ((e = hipMemcpyAsync(dp, hp, pbytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
+        return hip_fail(e, "query: upload parameters");
+    if ((e = hipEventRecord(c->staging_free, stream)) != hipSuccess) return hip_fail(e, "query: record");
+    c->staging_valid = true;
+
+    const QueryDev* dq = reinterpret_cast<const QueryDev*>(dp);
+    const int32_t* dql = reinterpret_cast<const int32_t*>(dp + off_ql);
+    int launches = 0;
+    int slot = -1;
+    if (c->timing) {
+        slot = c->next_slot;
+        c->next_slot = (c->next_slot + 1) % wmd_corpus::kTimingSlots;
+        if (c->slot_pending[slot] && (rc = fold_timing_slot(c, slot))) return rc;
+        (void)hipEventRecord(c->ev[slot][0], stream);
+    }
+    if ((e = launch_dist(dc, dq, B, max_m, opt.precision == WMD_DIST_BF16, stream)) != hipSuccess)
+        return hip_fail(e, "query: distance kernel launch");
+    ++launches;
+    if (slot >= 0) (void)hipEventRecord(c->ev[slot][1], stream);
+
+    const int d_tile = (int)c->d_tile;   // sorted docs [d_tile, N) fit the register tiles
+    for (int it0 = 0;; it0 += per_launch) {
+        SinkArgs a;
+        a.qd = dq;
+        a.sptr = dc.sptr;
+        a.scol = dc.scol;
+        a.scw = dc.scw;
+        a.sdoc = dc.sdoc;
+        a.it_begin = it0;
+        a.it_count = per_launch;
+        a.final_step = (int64_t)it0 + per_launch >= max_iters ? 1 : 0;
+        auto go = [&](int shape, int q0, int q1, int d0, int d1) -> hipError_t {
+            if (q1 <= q0 || d1 <= d0) return hipSuccess;
+            a.qlist = dql + q0;
+            a.nq = q1 - q0;
+            a.d_begin = d0;
+            a.d_end = d1;
+            int mm = 0;
+            for (int i = q0; i < q1; ++i) mm = std::max(mm, qs[hql[i]].m);
+            ++launches;
+            return launch_sinkhorn(shape, a, mm, c->h_sorted_len[d0], stream);
+        };
+        // queries too long for any register tile: streaming kernel over every document
+        if ((e = go(-1, start[0], start[1], 0, (int)N)) != hipSuccess) return hip_fail(e, "query: sinkhorn launch");
+        // documents too long for the register tiles: streaming kernel
+        if ((e = go(-1, start[1], B, 0, d_tile)) != hipSuccess) return hip_fail(e, "query: sinkhorn launch");
+        for (int s = 0; s < nshape; ++s)
+            if ((e = go(s, start[s + 1], start[s + 2], d_tile, (int)N)) != hipSuccess)
+                return hip_fail(e, "query: sinkhorn launch");
+        if (a.final_step) break;
+    }
+    if (slot >= 0) {
+        (void)hipEventRecord(c->ev[slot][2], stream);
+        c->slot_pending[slot] = true;
+        c->last_slot = slot;
+    }
+    c->last_launches = launches;
+    if ((e = hipEventRecord(c->done, stream)) != hipSuccess) return hip_fail(e, "query: record");
+    c->done_valid = true;
+    return WMD_OK;
+}
+
+}  // namespace wmd
+
+using namespace wmd;
+
+// ---------------------------------------------------------------- C ABI
+
+extern "C" {
+
+const char* wmd_last_error(void) { return g_err.c_str(); }
+
+void wmd_corpus_options_init(wmd_corpus_options* opt) {
+    if (!opt) return;
+    opt->device = -1;
+    opt->bf16 = 0;
+}
+
+void wmd_query_options_init(wmd_query_options* opt) {
+    if (!opt) return;
+    opt->precision = WMD_DIST_FP32;
+    opt->recompute_below = -1.f;
+    opt->log_domain = 0;
+    opt->iters_per_launch = 0;
+}
+
+static void corpus_free(wmd_corpus* c) {
+    DevCorpus& d = c->dc;
+    dfree(d.vecs);
+    dfree(d.act);
+    dfree(d.act_norm);
+    dfree(d.act_word);
+    dfree(d.act_bf16);
+    dfree(d.act_norm_bf16);
+    dfree(d.sptr);
+    dfree(d.scol);
+    dfree(d.scw);
+    dfree(d.sdoc);
+    Workspace& w = c->ws;
+    dfree(w.Kt);
+    dfree(w.KMt);
+    dfree(w.x);
+    dfree(w.params);
+    dfree(w.out);
+    hfree(w.h_params);
+    hfree(w.h_out);
+    for (int i = 0; i < wmd_corpus::kTimingSlots; ++i)
+        for (int j = 0; j < 3; ++j)
+            if (c->ev[i][j]) (void)hipEventDestroy(c->ev[i][j]);
+    if (c->done) (void)hipEventDestroy(c->done);
+    if (c->staging_free) (void)hipEventDestroy(c->staging_free);
+    if (c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+int wmd_corpus_create(const float* vecs, int64_t V, int32_t dim, const int64_t* doc_ptr,
+                      const int32_t* word_ids, const float* weights, int64_t N,
+                      const wmd_corpus_options* opt_in, wmd_corpus** out) {
+    if (!out) return fail(WMD_EINVAL, "corpus: null output handle");
+    if (!vecs || !doc_ptr || (!word_ids && N > 0) || (!weights && N > 0))
+        return fail(WMD_EINVAL, "corpus: null input array");
+    if (V <= 0 || V > INT32_MAX) return fail(WMD_EINVAL, "corpus: V must be in [1, 2^31)");
+    if (dim <= 0) return fail(WMD_EINVAL, "corpus: dim must be > 0");
+    if (N <= 0 || N > INT32_MAX) return fail(WMD_EINVAL, "corpus: N must be in [1, 2^31)");
+    wmd_corpus_options opt;
+    wmd_corpus_options_init(&opt);
+    if (opt_in) opt = *opt_in;
+    if (doc_ptr[0] != 0) return fail(WMD_EINVAL, "corpus: doc_ptr[0] must be 0");
+    for (int64_t j = 0; j < N; ++j)
+        if (doc_ptr[j + 1] < doc_ptr[j]) return fail(WMD_EINVAL, "corpus: doc_ptr decreases at %lld", (long long)j);
+    const int64_t nnz_in = doc_ptr[N];
+
+    // validate, drop zero weights, mark the vocabulary in use
+    std::vector<int32_t> stamp((size_t)V, -1);
+    std::vector<int32_t> remap((size_t)V, -1);
+    std::vector<int32_t> len((size_t)N);
+    std::vector<int32_t> ids;
+    std::vector<float> wts;
+    std::vector<int64_t> fptr((size_t)N + 1, 0);
+    ids.reserve((size_t)nnz_in);
+    wts.reserve((size_t)nnz_in);
+    for (int64_t j = 0; j < N; ++j) {
+        for (int64_t p = doc_ptr[j]; p < doc_ptr[j + 1]; ++p) {
+            const int32_t id = word_ids[p];
+            const float wt = weights[p];
+            if (id < 0 || id >= V) return fail(WMD_EINVAL, "corpus: document %lld has word id %d out of range", (long long)j, id);
+            if (stamp[id] == (int32_t)j) return fail(WMD_EINVAL, "corpus: document %lld repeats word %d", (long long)j, id);
+            stamp[id] = (int32_t)j;
+            if (!std::isfinite(wt) || wt < 0.f)
+                return fail(WMD_EINVAL, "corpus: document %lld has a negative or non-finite weight", (long long)j);
+            if (wt > 0.f) {
+                ids.push_back(id);
+                wts.push_back(wt);
+                remap[id] = 0;
+            }
+        }
+        fptr[j + 1] = (int64_t)ids.size();
+        len[j] = (int32_t)(fptr[j + 1] - fptr[j]);
+        if (len[j] == 0) return fail(WMD_EINVAL, "corpus: document %lld has no word with positive weight", (long long)j);
+        if (len[j] > kMaxDocWords)
+            return fail(WMD_EINVAL, "corpus: document %lld has %d words, above the limit of %d", (long long)j, len[j], kMaxDocWords);
+    }
+    const int64_t nnz = (int64_t)ids.size();
+    if (nnz > INT32_MAX) return fail(WMD_EINVAL, "corpus: more than 2^31-1 nonzeros");
+    std::vector<int32_t> act_word;
+    for (int64_t i = 0; i < V; ++i)
+        if (remap[i] == 0) {
+            remap[i] = (int32_t)act_word.size();
+            act_word.push_back((int32_t)i);
+        }
+    const int64_t U = (int64_t)act_word.size();
+    // documents sorted by length, longest first (stable)
+    std::vector<int32_t> order((size_t)N);
+    for (int64_t j = 0; j < N; ++j) order[j] = (int32_t)j;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return len[x] > len[y]; });
+    std::vector<int32_t> sptr((size_t)N + 1, 0), scol((size_t)nnz), slen((size_t)N);
+    std::vector<float> sw((size_t)nnz);
+    for (int64_t d = 0; d < N; ++d) {
+        const int32_t j = order[d];
+        slen[d] = len[j];
+        sptr[d + 1] = sptr[d] + len[j];
+        for (int32_t t = 0; t < len[j]; ++t) {
+            scol[sptr[d] + t] = remap[ids[fptr[j] + t]];
+            sw[sptr[d] + t] = wts[fptr[j] + t];
+        }
+    }
+
+    int dev = opt.device;
+    if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return fail(WMD_EDEVICE, "corpus: no current HIP device");
+    DeviceGuard guard(dev);
+    if (!guard.ok()) return fail(WMD_EDEVICE, "corpus: cannot select HIP device %d", dev);
+
+    wmd_corpus* c = new wmd_corpus();
+    DevCorpus& d = c->dc;
+    d.device = dev;
+    d.V = V;
+    d.N = N;
+    d.nnz = nnz;
+    d.U = U;
+    d.dim = dim;
+    d.ldv = (int32_t)align_up((size_t)dim, kRowAlign);
+    d.max_doc = slen[0];
+    c->h_sorted_len = slen;
+    c->h_sorted_len.push_back(0);
+    c->d_tile = 0;
+    while (c->d_tile < N && slen[c->d_tile] > kTileMaxDoc) ++c->d_tile;
+
+    hipError_t e = hipSuccess;
+    auto bail = [&](hipError_t err, const char* what) {
+        int code = hip_fail(err, what);
+        (void)hipDeviceSynchronize();
+        corpus_free(c);
+        return code;
+    };
+    if ((e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess) return bail(e, "corpus: stream");
+    if ((e = hipEventCreateWithFlags(&c->done, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&c->staging_free, hipEventDisableTiming)) != hipSuccess)
+        return bail(e, "corpus: events");
+    for (int i = 0; i < wmd_corpus::kTimingSlots; ++i)
+        for (int j = 0; j < 3; ++j)
+            if ((e = hipEventCreate(&c->ev[i][j])) != hipSuccess) return bail(e, "corpus: timing events");
+    const size_t ldv = (size_t)d.ldv;
+    if ((e = dalloc(&d.vecs, (size_t)V * ldv)) != hipSuccess || (e = dalloc(&d.act, (size_t)U * ldv)) != hipSuccess ||
+        (e = dalloc(&d.act_norm, (size_t)U)) != hipSuccess || (e = dalloc(&d.act_word, (size_t)U)) != hipSuccess ||
+        (e = dalloc(&d.sptr, (size_t)N + 1)) != hipSuccess || (e = dalloc(&d.scol, (size_t)nnz)) != hipSuccess ||
+        (e = dalloc(&d.scw, (size_t)nnz)) != hipSuccess || (e = dalloc(&d.sdoc, (size_t)N)) != hipSuccess)
+        return bail(e, "corpus: device allocation");
+    if (opt.bf16) {
+        if ((e = dalloc(&d.act_bf16, (size_t)U * ldv)) != hipSuccess ||
+            (e = dalloc(&d.act_norm_bf16, (size_t)U)) != hipSuccess)
+            return bail(e, "corpus: BF16 allocation");
+    }
+    hipStream_t s = c->stream;
+    if ((e = hipMemsetAsync(d.vecs, 0, (size_t)V * ldv * sizeof(float), s)) != hipSuccess ||
+        (e = hipMemcpy2DAsync(d.vecs, ldv * sizeof(float), vecs, (size_t)dim * sizeof(float),
+                              (size_t)dim * sizeof(float), (size_t)V, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(d.act_word, act_word.data(), sizeof(int32_t) * U, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(d.sptr, sptr.data(), sizeof(int32_t) * (N + 1), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(d.scol, scol.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(d.scw, sw.data(), sizeof(float) * nnz, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(d.sdoc, order.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, s)) != hipSuccess)
+        return bail(e, "corpus: upload");
+    if ((e = launch_gather_rows(d.vecs, d.act_word, d.act, U, d.ldv, s)) != hipSuccess ||
+        (e = launch_prep_norms(d.act, U, d.ldv, d.act_norm, s)) != hipSuccess ||
+        (e = launch_prep_docs(d.sptr, d.scw, d.scw, N, s)) != hipSuccess)
+        return bail(e, "corpus: preparation kernels");
+    if (opt.bf16 && (e = launch_prep_bf16(d.act, d.act_bf16, d.act_norm_bf16, U, d.ldv, s)) != hipSuccess)
+        return bail(e, "corpus: BF16 preparation");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return bail(e, "corpus: preparation");
+    c->device_bytes = (int64_t)((V + U) * ldv * sizeof(float) + U * (sizeof(float) + sizeof(int32_t)) +
+                                (N + 1 + N) * sizeof(int32_t) + nnz * (sizeof(int32_t) + sizeof(float)) +
+                                (opt.bf16 ? U * (ldv * sizeof(uint16_t) + sizeof(float)) : 0));
+    *out = c;
+    return WMD_OK;
+}
+
+void wmd_corpus_destroy(wmd_corpus* c) {
+    if (!c) return;
+    DeviceGuard guard(c->dc.device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->done_valid) (void)hipEventSynchronize(c->done);
+    corpus_free(c);
+}
+
+int wmd_corpus_info_get(const wmd_corpus* c, wmd_corpus_info* out) {
+    if (!c || !out) return fail(WMD_EINVAL, "info: null argument");
+    out->V = c->dc.V;
+    out->N = c->dc.N;
+    out->nnz = c->dc.nnz;
+    out->U = c->dc.U;
+    out->dim = c->dc.dim;
+    out->max_doc_words = c->dc.max_doc;
+    out->device = c->dc.device;
+    out->has_bf16 = c->dc.act_bf16 != nullptr;
+    out->device_bytes = c->device_bytes;
+    return WMD_OK;
+}
+
+static int check_opts(const wmd_query_options* in, wmd_query_options* o) {
+    wmd_query_options_init(o);
+    if (in) *o = *in;
+    if (o->precision != WMD_DIST_FP32 && o->precision != WMD_DIST_BF16)
+        return fail(WMD_EINVAL, "options: unknown precision %d", o->precision);
+    if (!std::isfinite(o->recompute_below)) return fail(WMD_EINVAL, "options: recompute_below not finite");
+    if (o->iters_per_launch < 0) return fail(WMD_EINVAL, "options: iters_per_launch < 0");
+    return WMD_OK;
+}
+
+static int batch_plan(wmd_corpus* c, int32_t B, const int64_t* q_ptr, const int32_t* qids, const float* qw,
+                      const float* lambdas, const int32_t* iters, const wmd_query_options& o,
+                      std::vector<PlannedQuery>* qs) {
+    if (B <= 0 || !q_ptr || !lambdas || !iters) return fail(WMD_EINVAL, "batch: bad arguments");
+    if (q_ptr[0] != 0) return fail(WMD_EINVAL, "batch: q_ptr[0] must be 0");
+    qs->resize(B);
+    for (int32_t b = 0; b < B; ++b) {
+        const int64_t n = q_ptr[b + 1] - q_ptr[b];
+        if (n <= 0 || n > INT32_MAX) return fail(WMD_EINVAL, "batch: query %d has no words", b);
+        int rc = plan_query(c, qids + q_ptr[b], qw + q_ptr[b], (int32_t)n, lambdas[b], iters[b],
+                            o.precision == WMD_DIST_BF16, &(*qs)[b]);
+        if (rc) {
+            std::string msg = g_err;
+            return fail(rc, "batch query %d: %s", b, msg.c_str());
+        }
+    }
+    return WMD_OK;
+}
+
+static int finish_sync(wmd_corpus* c, int B, double* out_dist, double* out_resid) {
+    Workspace& w = c->ws;
+    const size_t n = (size_t)B * c->dc.N;
+    const size_t bytes = sizeof(double) * n * (out_resid ? 2 : 1);
+    hipError_t e;
+    if ((e = hipMemcpyAsync(w.h_out, w.out, bytes, hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+        return hip_fail(e, "query: download results");
+    if ((e = hipEventRecord(c->done, c->stream)) != hipSuccess) return hip_fail(e, "query: record");
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(e, "query: execution");
+    std::memcpy(out_dist, w.h_out, sizeof(double) * n);
+    if (out_resid) std::memcpy(out_resid, w.h_out + n, sizeof(double) * n);
+    return WMD_OK;
+}
+
+int wmd_query(wmd_corpus* c, const int32_t* qids, const float* qweights, int32_t n, float lambda, int32_t iters,
+              const wmd_query_options* opt, double* out_dist, double* out_resid) {
+    if (!c || !out_dist) return fail(WMD_EINVAL, "query: null corpus or output");
+    wmd_query_options o;
+    int rc = check_opts(opt, &o);
+    if (rc) return rc;
+    std::vector<PlannedQuery> qs(1);
+    if ((rc = plan_query(c, qids, qweights, n, lambda, iters, o.precision == WMD_DIST_BF16, &qs[0]))) return rc;
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard guard(c->dc.device);
+    if (!guard.ok()) return fail(WMD_EDEVICE, "query: cannot select device");
+    double dummy = 0.0;
+    if ((rc = run_queries(c, qs, o, &dummy, out_resid ? &dummy : nullptr, c->stream, true))) return rc;
+    return finish_sync(c, 1, out_dist, out_resid);
+}
+
+int wmd_query_async(wmd_corpus* c, const int32_t* qids, const float* qweights, int32_t n, float lambda,
+                    int32_t iters, const wmd_query_options* opt, double* dev_dist, double* dev_resid,
+                    void* stream) {
+    if (!c || !dev_dist) return fail(WMD_EINVAL, "query: null corpus or output");
+    wmd_query_options o;
+    int rc = check_opts(opt, &o);
+    if (rc) return rc;
+    std::vector<PlannedQuery> qs(1);
+    if ((rc = plan_query(c, qids, qweights, n, lambda, iters, o.precision == WMD_DIST_BF16, &qs[0]))) return rc;
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard guard(c->dc.device);
+    if (!guard.ok()) return fail(WMD_EDEVICE, "query: cannot select device");
+    return run_queries(c, qs, o, dev_dist, dev_resid, (hipStream_t)stream, false);
+}
+
+int wmd_query_batch(wmd_corpus* c, int32_t B, const int64_t* q_ptr, const int32_t* qids, const float* qweights,
+                    const float* lambdas, const int32_t* iters, const wmd_query_options* opt, double* out_dist,
+                    double* out_resid) {
+    if (!c || !out_dist) return fail(WMD_EINVAL, "batch: null corpus or output");
+    wmd_query_options o;
+    int rc = check_opts(opt, &o);
+    if (rc) return rc;
+    std::vector<PlannedQuery> qs;
+    if ((rc = batch_plan(c, B, q_ptr, qids, qweights, lambdas, iters, o, &qs))) return rc;
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard guard(c->dc.device);
+    if (!guard.ok()) return fail(WMD_EDEVICE, "batch: cannot select device");
+    double dummy = 0.0;
+    if ((rc = run_queries(c, qs, o, &dummy, out_resid ? &dummy : nullptr, c->stream, true))) return rc;
+    return finish_sync(c, B, out_dist, out_resid);
+}
+
+int wmd_query_batch_async(wmd_corpus* c, int32_t B, const int64_t* q_ptr, const int32_t* qids,
+                          const float* qweights, const float* lambdas, const int32_t* iters,
+                          const wmd_query_options* opt, double* dev_dist, double* dev_resid, void* stream) {
+    if (!c || !dev_dist) return fail(WMD_EINVAL, "batch: null corpus or output");
+    wmd_query_options o;
+    int rc = check_opts(opt, &o);
+    if (rc) return rc;
+    std::vector<PlannedQuery> qs;
+    if ((rc = batch_plan(c, B, q_ptr, qids, qweights, lambdas, iters, o, &qs))) return rc;
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard guard(c->dc.device);
+    if (!guard.ok()) return fail(WMD_EDEVICE, "batch: cannot select device");
+    return run_queries(c, qs, o, dev_dist, dev_resid, (hipStream_t)stream, false);
+}
+
+int wmd_set_timing(wmd_corpus* c, int32_t enable) {
+    if (!c) return fail(WMD_EINVAL, "timing: null corpus");
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard guard(c->dc.device);
+    for (int i = 0; i < wmd_corpus::kTimingSlots; ++i)
+        if (c->slot_pending[i]) {
+            hipError_t e = hipEventSynchronize(c->ev[i][2]);
+            if (e != hipSuccess) return hip_fail(e, "timing: wait");
+            c->slot_pending[i] = false;
+        }
+    c->timing = enable != 0;
+    c->timed_calls = 0;
+    c->dist_ms_total = c->sink_ms_total = 0.0;
+    c->last_dist_ms = c->last_sink_ms = 0.f;
+    c->last_slot = -1;
+    return WMD_OK;
+}
+
+int wmd_timing_get(wmd_corpus* c, wmd_timing* out) {
+    if (!c || !out) return fail(WMD_EINVAL, "timing: null argument");
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard guard(c->dc.device);
+    for (int i = 0; i < wmd_corpus::kTimingSlots; ++i) {
+        const int slot = (c->next_slot + i) % wmd_corpus::kTimingSlots;   // oldest first
+        if (c->slot_pending[slot]) {
+            int rc = fold_timing_slot(c, slot);
+            if (rc) return rc;
+        }
+    }
+    out->calls = c->timed_calls;
+    out->dist_ms = c->dist_ms_total;
+    out->sinkhorn_ms = c->sink_ms_total;
+    out->last_dist_ms = c->last_dist_ms;
+    out->last_sinkhorn_ms = c->last_sink_ms;
+    out->launches = c->last_launches;
+    return WMD_OK;
+}
+
+}  // extern "C"

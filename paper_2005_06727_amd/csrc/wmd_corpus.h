@@ -1,0 +1,89 @@
+// Host-side state of a corpus and its query workspace.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "wmd_internal.h"
+
+namespace wmd {
+
+constexpr int kMaxQueryWords = 4096;   // streaming kernel LDS: 3 floats per query word
+constexpr int kMaxDocWords = 16384;    // streaming kernel LDS: 1 float per document word
+constexpr int kTileMaxDoc = 64;        // documents up to this length use the register tiles
+
+struct Workspace {
+    float* Kt = nullptr;
+    float* KMt = nullptr;
+    size_t kcap = 0;          // floats in each of Kt, KMt
+    float* x = nullptr;
+    size_t xcap = 0;
+    char* params = nullptr;   // device parameter block
+    char* h_params = nullptr; // pinned staging of the parameter block
+    size_t pcap = 0;
+    double* out = nullptr;    // device results of synchronous calls
+    size_t ocap = 0;          // bytes
+    double* h_out = nullptr;  // pinned copy of `out`
+    size_t hocap = 0;
+};
+
+struct PlannedQuery {
+    std::vector<int32_t> ids;    // words with positive weight, input order
+    std::vector<float> r, rinv;  // r_k (sum 1) and 1 / r_k, each rounded once from FP64
+    int m = 0, ldk = 0, iters = 0;
+    float lambda = 0.f;
+};
+
+class DeviceGuard {
+  public:
+    explicit DeviceGuard(int dev);
+    ~DeviceGuard();
+    bool ok() const { return ok_; }
+
+  private:
+    int dev_, prev_ = -1;
+    bool ok_ = false;
+};
+
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+extern thread_local std::string g_err;
+
+}  // namespace wmd
+
+struct wmd_corpus {
+    wmd::DevCorpus dc;
+    std::vector<int32_t> h_sorted_len;  // document lengths in sorted order, plus a trailing 0
+    int64_t d_tile = 0;                 // first sorted document that fits the register tiles
+    int64_t device_bytes = 0;
+    std::mutex mu;
+    hipStream_t stream = nullptr;       // stream of the synchronous entry points
+    hipEvent_t done = nullptr;          // end of the most recent call's work
+    bool done_valid = false;
+    hipEvent_t staging_free = nullptr;  // the last parameter upload has been consumed
+    bool staging_valid = false;
+    // timing ring: slot i holds the events of one timed call (start, after
+    // the distance kernel, end); a slot is folded into the totals before reuse
+    static constexpr int kTimingSlots = 64;
+    hipEvent_t ev[kTimingSlots][3] = {};
+    bool slot_pending[kTimingSlots] = {};
+    int next_slot = 0, last_slot = -1;
+    bool timing = false;
+    int64_t timed_calls = 0;
+    double dist_ms_total = 0.0, sink_ms_total = 0.0;
+    float last_dist_ms = 0.f, last_sink_ms = 0.f;
+    int last_launches = 0;
+    wmd::Workspace ws;
+};
+
+namespace wmd {
+int plan_query(const wmd_corpus* c, const int32_t* qids, const float* qw, int32_t n, float lambda,
+               int32_t iters, int bf16, PlannedQuery* out);
+int run_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_query_options& opt,
+                double* dev_out, double* dev_res, hipStream_t stream, bool need_host_out);
+int fold_timing_slot(wmd_corpus* c, int slot);
+}  // namespace wmd

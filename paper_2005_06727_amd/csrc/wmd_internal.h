@@ -1,0 +1,89 @@
+// Internal declarations shared by the host runtime and the HIP kernels of libwmd.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "wmd.h"
+
+namespace wmd {
+
+// Embedding rows on the device are zero-padded to a multiple of this many
+// floats, so the distance GEMM's k loop needs no tail handling.
+constexpr int kRowAlign = 64;
+
+// Per-query descriptor in device memory, read by every kernel of a query.
+struct QueryDev {
+    const int32_t* qid;    // m vocabulary ids of the query words
+    const float* r;        // m query weights r_k (sum 1)
+    const float* rinv;     // m values 1 / r_k
+    float* Kt;             // U x ldk: Kt[i, k] = K[k, word(i)] (optionally column-shifted)
+    float* KMt;            // U x ldk: Kt[i, k] * M[k, word(i)]
+    float* x;              // N x ldk iterate x (documents in length-sorted order),
+                           // used only when iterations span several launches
+    double* out;           // N distances, input document order
+    double* resid;         // N row-marginal residuals or nullptr
+    float lambda;
+    float tau2;            // squared recompute threshold of the distance epilogue
+    int32_t m;             // query words (v_r)
+    int32_t ldk;           // row stride of Kt / KMt / x (multiple of 4, >= m)
+    int32_t iters;         // x updates
+    int32_t shift;         // log-domain column shift on/off
+};
+
+// Device-resident corpus (all arrays on `device`).
+struct DevCorpus {
+    int device = 0;
+    int64_t V = 0, N = 0, nnz = 0, U = 0;
+    int32_t dim = 0, ldv = 0, max_doc = 0;
+    float* vecs = nullptr;          // V x ldv FP32, every vocabulary word
+    float* act = nullptr;           // U x ldv FP32, the words the documents use
+    float* act_norm = nullptr;      // U: |row|^2 of act
+    int32_t* act_word = nullptr;    // U: vocabulary id of each act row
+    uint16_t* act_bf16 = nullptr;   // U x ldv BF16 copy of act (optional)
+    float* act_norm_bf16 = nullptr; // U: |bf16 row|^2 (optional)
+    int32_t* sptr = nullptr;        // N+1: CSR row pointer, documents sorted by length desc
+    int32_t* scol = nullptr;        // nnz: act row index of each nonzero
+    float* scw = nullptr;           // nnz: normalised weight c_ij
+    int32_t* sdoc = nullptr;        // N: input id of each sorted document
+};
+
+// Arguments of one fused Sinkhorn launch: every (query, document) pair with
+// query in qlist[0..nq) and document rank in [d_begin, d_end).
+struct SinkArgs {
+    const QueryDev* qd;
+    const int32_t* qlist;
+    int32_t nq;
+    int32_t d_begin, d_end;
+    const int32_t* sptr;
+    const int32_t* scol;
+    const float* scw;
+    const int32_t* sdoc;
+    int32_t it_begin;      // first iteration index handled by this launch
+    int32_t it_count;      // iterations in this launch (clamped to each query's iters)
+    int32_t final_step;    // nonzero: run the final u/v/WMD step at the end
+};
+
+// ---- launchers (return hipError_t of the launch) ----
+hipError_t launch_prep_norms(const float* rows, int64_t nrows, int ldv, float* norms, hipStream_t s);
+hipError_t launch_prep_bf16(const float* src, uint16_t* dst, float* norms, int64_t nrows, int ldv,
+                            hipStream_t s);
+hipError_t launch_prep_docs(const int32_t* ptr, const float* w, float* cw, int64_t N, hipStream_t s);
+hipError_t launch_gather_rows(const float* vecs, const int32_t* ids, float* out, int64_t nrows, int ldv,
+                              hipStream_t s);
+
+// Distance GEMM + epilogue for queries qd[0..B): writes Kt / KMt.
+hipError_t launch_dist(const DevCorpus& c, const QueryDev* qd, int B, int max_m, int bf16,
+                       hipStream_t s);
+
+// Fused Sinkhorn iterations + final WMD step.  `shape` selects the register
+// tile (see k_sinkhorn.hip); shape < 0 selects the streaming kernel that
+// handles any size.
+int sinkhorn_shape_for(int m, int max_n);   // -1 when only the streaming kernel fits
+int sinkhorn_shape_max_m(int shape);
+int sinkhorn_shape_max_n(int shape);
+hipError_t launch_sinkhorn(int shape, const SinkArgs& a, int max_m, int max_n, hipStream_t s);
+
+}  // namespace wmd

@@ -1,0 +1,284 @@
+"""ctypes binding of libwmd (include/wmd.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls; all the
+arithmetic runs in the library's HIP kernels.  Importing this module loads
+``libwmd.so`` and raises ImportError when it has not been built
+(``python -m paper_2005_06727_amd.build``).
+
+torch, when importable, is imported before the library so that the process
+holds a single HIP runtime (torch ships its own copy under the same soname);
+it is used only for device buffers and streams of the ``*_async`` calls.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+try:  # one HIP runtime per process: let torch's copy be the one
+    import torch
+except ImportError:  # pragma: no cover - torch is part of the image
+    torch = None
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libwmd.so")
+HEADER = os.path.join(os.path.dirname(PKG), "include", "wmd.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run: python -m paper_2005_06727_amd.build")
+_lib = C.CDLL(LIB_PATH)
+
+WMD_OK, WMD_EINVAL, WMD_ENOMEM, WMD_EDEVICE = 0, -1, -2, -3
+WMD_ETIMEDOUT, WMD_ESHUTDOWN, WMD_ENOTFOUND = -4, -5, -6
+WMD_DIST_FP32, WMD_DIST_BF16 = 0, 1
+
+
+class WmdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libwmd error {code}: {msg}")
+        self.code = code
+
+
+class wmd_corpus_options(C.Structure):
+    _fields_ = [("device", C.c_int32), ("bf16", C.c_int32)]
+
+
+class wmd_query_options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("recompute_below", C.c_float),
+                ("log_domain", C.c_int32), ("iters_per_launch", C.c_int32)]
+
+
+class wmd_corpus_info(C.Structure):
+    _fields_ = [("V", C.c_int64), ("N", C.c_int64), ("nnz", C.c_int64), ("U", C.c_int64),
+                ("dim", C.c_int32), ("max_doc_words", C.c_int32), ("device", C.c_int32),
+                ("has_bf16", C.c_int32), ("device_bytes", C.c_int64)]
+
+
+class wmd_timing(C.Structure):
+    _fields_ = [("calls", C.c_int64), ("dist_ms", C.c_double), ("sinkhorn_ms", C.c_double),
+                ("last_dist_ms", C.c_float), ("last_sinkhorn_ms", C.c_float), ("launches", C.c_int32)]
+
+
+_P = C.c_void_p
+_i32p, _i64p = C.POINTER(C.c_int32), C.POINTER(C.c_int64)
+_f32p, _f64p = C.POINTER(C.c_float), C.POINTER(C.c_double)
+
+
+def _sig(name, res, *args):
+    f = getattr(_lib, name)
+    f.restype, f.argtypes = res, list(args)
+    return f
+
+
+_sig("wmd_last_error", C.c_char_p)
+_sig("wmd_corpus_options_init", None, C.POINTER(wmd_corpus_options))
+_sig("wmd_query_options_init", None, C.POINTER(wmd_query_options))
+_sig("wmd_corpus_create", C.c_int, _f32p, C.c_int64, C.c_int32, _i64p, _i32p, _f32p, C.c_int64,
+     C.POINTER(wmd_corpus_options), C.POINTER(_P))
+_sig("wmd_corpus_destroy", None, _P)
+_sig("wmd_corpus_info_get", C.c_int, _P, C.POINTER(wmd_corpus_info))
+_sig("wmd_query", C.c_int, _P, _i32p, _f32p, C.c_int32, C.c_float, C.c_int32,
+     C.POINTER(wmd_query_options), _f64p, _f64p)
+_sig("wmd_query_async", C.c_int, _P, _i32p, _f32p, C.c_int32, C.c_float, C.c_int32,
+     C.POINTER(wmd_query_options), _P, _P, _P)
+_sig("wmd_query_batch", C.c_int, _P, C.c_int32, _i64p, _i32p, _f32p, _f32p, _i32p,
+     C.POINTER(wmd_query_options), _f64p, _f64p)
+_sig("wmd_query_batch_async", C.c_int, _P, C.c_int32, _i64p, _i32p, _f32p, _f32p, _i32p,
+     C.POINTER(wmd_query_options), _P, _P, _P)
+_sig("wmd_set_timing", C.c_int, _P, C.c_int32)
+_sig("wmd_timing_get", C.c_int, _P, C.POINTER(wmd_timing))
+
+
+def declared_functions() -> list:
+    """Names of the functions include/wmd.h declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w]+\s*\*?\s*(wmd_\w+)\s*\(", text, flags=re.M)))
+
+
+def exported(name: str) -> bool:
+    return hasattr(_lib, name)
+
+
+def wmd_last_error() -> str:
+    return (_lib.wmd_last_error() or b"").decode()
+
+
+def _check(rc: int) -> None:
+    if rc != WMD_OK:
+        raise WmdError(rc, wmd_last_error())
+
+
+def _arr(a, dtype) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a), dtype=dtype)
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _qopts(precision=WMD_DIST_FP32, recompute_below=-1.0, log_domain=False, iters_per_launch=0):
+    o = wmd_query_options()
+    _lib.wmd_query_options_init(C.byref(o))
+    o.precision = int(precision)
+    o.recompute_below = float(recompute_below)
+    o.log_domain = int(bool(log_domain))
+    o.iters_per_launch = int(iters_per_launch)
+    return o
+
+
+def _devptr(x) -> Optional[int]:
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if torch is not None and isinstance(x, torch.Tensor):
+        if not x.is_cuda or x.dtype != torch.float64 or not x.is_contiguous():
+            raise ValueError("device outputs must be contiguous float64 GPU tensors")
+        return x.data_ptr()
+    raise TypeError("device pointer must be an int or a torch tensor")
+
+
+def _stream(s) -> Optional[int]:
+    if s is None:
+        return torch.cuda.current_stream().cuda_stream if torch is not None else None
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def wmd_corpus_options_init() -> wmd_corpus_options:
+    o = wmd_corpus_options()
+    _lib.wmd_corpus_options_init(C.byref(o))
+    return o
+
+
+def wmd_query_options_init() -> wmd_query_options:
+    o = wmd_query_options()
+    _lib.wmd_query_options_init(C.byref(o))
+    return o
+
+
+def wmd_corpus_create(vecs, doc_ptr, word_ids, weights, device: int = -1, bf16: bool = False) -> int:
+    v = _arr(vecs, np.float32)
+    if v.ndim != 2:
+        raise ValueError("vecs must be V x dim")
+    p, ids, w = _arr(doc_ptr, np.int64), _arr(word_ids, np.int32), _arr(weights, np.float32)
+    if p.ndim != 1 or p.size < 1 or ids.shape != w.shape or int(p[-1]) > ids.size:
+        raise ValueError("doc_ptr / word_ids / weights do not form a CSR")
+    o = wmd_corpus_options_init()
+    o.device, o.bf16 = int(device), int(bool(bf16))
+    h = _P()
+    _check(_lib.wmd_corpus_create(_ptr(v, C.c_float), v.shape[0], v.shape[1], _ptr(p, C.c_int64),
+                                  _ptr(ids, C.c_int32), _ptr(w, C.c_float), p.size - 1,
+                                  C.byref(o), C.byref(h)))
+    return h.value
+
+
+def wmd_corpus_destroy(corpus: int) -> None:
+    _lib.wmd_corpus_destroy(corpus)
+
+
+def wmd_corpus_info_get(corpus: int) -> dict:
+    info = wmd_corpus_info()
+    _check(_lib.wmd_corpus_info_get(corpus, C.byref(info)))
+    return {f: getattr(info, f) for f, _ in info._fields_}
+
+
+def wmd_query(corpus: int, qids, qweights, lam: float, iters: int, resid: bool = False,
+              **opts) -> Tuple[np.ndarray, Optional[np.ndarray]]:
+    q, w = _arr(qids, np.int32), _arr(qweights, np.float32)
+    if q.shape != w.shape or q.ndim != 1:
+        raise ValueError("query ids and weights must be 1-D of equal length")
+    N = wmd_corpus_info_get(corpus)["N"]
+    out = np.empty(N, np.float64)
+    res = np.empty(N, np.float64) if resid else None
+    o = _qopts(**opts)
+    _check(_lib.wmd_query(corpus, _ptr(q, C.c_int32), _ptr(w, C.c_float), q.size, float(lam), int(iters),
+                          C.byref(o), _ptr(out, C.c_double), _ptr(res, C.c_double) if resid else None))
+    return out, res
+
+
+def wmd_query_async(corpus: int, qids, qweights, lam: float, iters: int, dev_dist, dev_resid=None,
+                    stream=None, **opts) -> None:
+    q, w = _arr(qids, np.int32), _arr(qweights, np.float32)
+    o = _qopts(**opts)
+    _check(_lib.wmd_query_async(corpus, _ptr(q, C.c_int32), _ptr(w, C.c_float), q.size, float(lam),
+                                int(iters), C.byref(o), _devptr(dev_dist), _devptr(dev_resid),
+                                _stream(stream)))
+
+
+def _batch_args(queries: Sequence[Tuple[np.ndarray, np.ndarray]], lambdas, iters):
+    B = len(queries)
+    qp = np.zeros(B + 1, np.int64)
+    qp[1:] = np.cumsum([len(q[0]) for q in queries])
+    ids = _arr(np.concatenate([np.asarray(q[0]) for q in queries]), np.int32)
+    w = _arr(np.concatenate([np.asarray(q[1]) for q in queries]), np.float32)
+    lam = _arr(np.broadcast_to(np.asarray(lambdas, np.float32), (B,)), np.float32)
+    it = _arr(np.broadcast_to(np.asarray(iters, np.int32), (B,)), np.int32)
+    return B, qp, ids, w, lam, it
+
+
+def wmd_query_batch(corpus: int, queries, lambdas, iters, resid: bool = False, **opts):
+    B, qp, ids, w, lam, it = _batch_args(queries, lambdas, iters)
+    N = wmd_corpus_info_get(corpus)["N"]
+    out = np.empty((B, N), np.float64)
+    res = np.empty((B, N), np.float64) if resid else None
+    o = _qopts(**opts)
+    _check(_lib.wmd_query_batch(corpus, B, _ptr(qp, C.c_int64), _ptr(ids, C.c_int32), _ptr(w, C.c_float),
+                                _ptr(lam, C.c_float), _ptr(it, C.c_int32), C.byref(o),
+                                _ptr(out, C.c_double), _ptr(res, C.c_double) if resid else None))
+    return out, res
+
+
+def wmd_query_batch_async(corpus: int, queries, lambdas, iters, dev_dist, dev_resid=None, stream=None,
+                          **opts) -> None:
+    B, qp, ids, w, lam, it = _batch_args(queries, lambdas, iters)
+    o = _qopts(**opts)
+    _check(_lib.wmd_query_batch_async(corpus, B, _ptr(qp, C.c_int64), _ptr(ids, C.c_int32),
+                                      _ptr(w, C.c_float), _ptr(lam, C.c_float), _ptr(it, C.c_int32),
+                                      C.byref(o), _devptr(dev_dist), _devptr(dev_resid), _stream(stream)))
+
+
+def wmd_set_timing(corpus: int, enable: bool) -> None:
+    _check(_lib.wmd_set_timing(corpus, int(bool(enable))))
+
+
+def wmd_timing_get(corpus: int) -> dict:
+    t = wmd_timing()
+    _check(_lib.wmd_timing_get(corpus, C.byref(t)))
+    return {f: getattr(t, f) for f, _ in t._fields_}
+
+
+class Corpus:
+    """Owning handle: ``Corpus(vecs, doc_ptr, word_ids, weights).query(ids, w, lam, iters)``."""
+
+    def __init__(self, vecs, doc_ptr, word_ids, weights, device: int = -1, bf16: bool = False):
+        self.handle = wmd_corpus_create(vecs, doc_ptr, word_ids, weights, device, bf16)
+        self.info = wmd_corpus_info_get(self.handle)
+
+    def query(self, qids, qweights, lam, iters, resid=False, **opts):
+        return wmd_query(self.handle, qids, qweights, lam, iters, resid, **opts)
+
+    def query_batch(self, queries, lambdas, iters, resid=False, **opts):
+        return wmd_query_batch(self.handle, queries, lambdas, iters, resid, **opts)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            wmd_corpus_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
