@@ -70,6 +70,12 @@ typedef struct wmd_query_options {
     int32_t iters_per_launch; /* 0: all iterations and the final step in one fused
                                  launch; k > 0: at most k iterations per launch, x kept
                                  in device memory between launches */
+    int32_t tile;             /* Sinkhorn launch shape: -1 picks by query length; 0..7
+                                 forces that register tile (WMD_EINVAL when the query is
+                                 longer than the tile holds); -2 uses the streaming
+                                 kernel for every document.  Results are identical
+                                 between calls with the same tile, and agree across
+                                 tiles to FP32 rounding. */
 } wmd_query_options;
 
 typedef struct wmd_corpus_info {
@@ -87,7 +93,7 @@ typedef struct wmd_corpus_info {
 void wmd_corpus_options_init(wmd_corpus_options* opt);
 
 /* Fill *opt with the defaults (FP32, recompute_below -1, no log domain,
- * fused launch). */
+ * fused launch, tile -1). */
 void wmd_query_options_init(wmd_query_options* opt);
 
 /*
@@ -151,8 +157,11 @@ int wmd_query(wmd_corpus* corpus, const int32_t* qids, const float* qweights,
  * before return), the outputs are DEVICE pointers to N doubles (dev_resid
  * nullable), written in stream order on `stream`.  The call returns after
  * enqueueing; argument errors are reported synchronously, device faults at
- * the caller's next synchronisation.  Calls on one corpus share its
- * workspace and are ordered after each other even across streams.
+ * the caller's next synchronisation.  A corpus has two workspace slots used in
+ * turn: consecutive calls on different streams may run concurrently, and a
+ * call never starts before the call that last used its slot has finished,
+ * whatever the streams.  Host-side state is locked, so threads may share a
+ * corpus.
  */
 int wmd_query_async(wmd_corpus* corpus, const int32_t* qids, const float* qweights,
                     int32_t n, float lambda, int32_t iters,

@@ -106,18 +106,16 @@ int plan_query(const wmd_corpus* c, const int32_t* qids, const float* qw, int32_
     return WMD_OK;
 }
 
-static int ensure_workspace(wmd_corpus* c, size_t kfloats, size_t xfloats, size_t pbytes, size_t obytes,
-                            bool need_host_out) {
-    Workspace& w = c->ws;
-    const bool grow = kfloats > w.kcap || xfloats > w.xcap || pbytes > w.pcap || obytes > w.ocap ||
-                      (need_host_out && obytes > w.hocap);
+static int ensure_workspace(Workspace& w, size_t kfloats, size_t xfloats, size_t nfloats, size_t pbytes,
+                            size_t obytes, bool need_host_out) {
+    const bool grow = kfloats > w.kcap || xfloats > w.xcap || nfloats > w.ncap || pbytes > w.pcap ||
+                      obytes > w.ocap || (need_host_out && obytes > w.hocap);
     if (!grow) return WMD_OK;
-    // nothing queued may still use the old buffers
-    if (c->done_valid) {
-        hipError_t e = hipEventSynchronize(c->done);
+    // nothing queued may still use this slot's old buffers
+    if (w.done_valid) {
+        hipError_t e = hipEventSynchronize(w.done);
         if (e != hipSuccess) return hip_fail(e, "workspace: wait for previous work");
     }
-    if (c->staging_valid) (void)hipEventSynchronize(c->staging_free);
     hipError_t e = hipSuccess;
     auto grown = [](size_t need) { return need + need / 4; };
     if (kfloats > w.kcap) {
@@ -136,16 +134,19 @@ static int ensure_workspace(wmd_corpus* c, size_t kfloats, size_t xfloats, size_
         if ((e = dalloc(&w.x, cap)) != hipSuccess) return hip_fail(e, "workspace: x buffer");
         w.xcap = cap;
     }
+    if (nfloats > w.ncap) {
+        dfree(w.nrow);
+        w.ncap = 0;
+        size_t cap = grown(nfloats);
+        if ((e = dalloc(&w.nrow, cap)) != hipSuccess) return hip_fail(e, "workspace: row shifts");
+        w.ncap = cap;
+    }
     if (pbytes > w.pcap) {
         dfree(w.params);
-        hfree(w.h_params);
         w.pcap = 0;
         size_t cap = grown(pbytes);
         if ((e = dalloc(&w.params, cap)) != hipSuccess) return hip_fail(e, "workspace: query parameters");
-        if ((e = hipHostMalloc(reinterpret_cast<void**>(&w.h_params), cap, hipHostMallocDefault)) != hipSuccess)
-            return hip_fail(e, "workspace: pinned staging");
         w.pcap = cap;
-        c->staging_valid = false;
     }
     if (obytes > w.ocap) {
         dfree(w.out);
@@ -163,6 +164,34 @@ static int ensure_workspace(wmd_corpus* c, size_t kfloats, size_t xfloats, size_
             return hip_fail(e, "workspace: pinned output");
         w.hocap = cap;
     }
+    return WMD_OK;
+}
+
+// A pinned staging slot of at least `bytes`, free for writing.
+static int take_staging(wmd_corpus* c, size_t bytes, int* slot_out) {
+    Staging& st = c->stage;
+    hipError_t e;
+    if (bytes > st.cap) {
+        for (int i = 0; i < Staging::kSlots; ++i) {
+            if (st.pending[i] && (e = hipEventSynchronize(st.ev[i])) != hipSuccess)
+                return hip_fail(e, "staging: wait");
+            st.pending[i] = false;
+            hfree(st.h[i]);
+        }
+        st.cap = 0;
+        const size_t cap = bytes + bytes / 4;
+        for (int i = 0; i < Staging::kSlots; ++i)
+            if ((e = hipHostMalloc(reinterpret_cast<void**>(&st.h[i]), cap, hipHostMallocDefault)) != hipSuccess)
+                return hip_fail(e, "staging: pinned allocation");
+        st.cap = cap;
+    }
+    const int slot = st.next;
+    st.next = (st.next + 1) % Staging::kSlots;
+    if (st.pending[slot]) {
+        if ((e = hipEventSynchronize(st.ev[slot])) != hipSuccess) return hip_fail(e, "staging: wait");
+        st.pending[slot] = false;
+    }
+    *slot_out = slot;
     return WMD_OK;
 }
 
@@ -188,7 +217,7 @@ int fold_timing_slot(wmd_corpus* c, int slot) {
 // Enqueue K1 + the fused Sinkhorn launches for `qs` on `stream`.  Row b of
 // dev_out (and dev_res when non-null) receives query b's N results.
 int run_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_query_options& opt,
-                double* dev_out, double* dev_res, hipStream_t stream, bool need_host_out) {
+                double* dev_out, double* dev_res, hipStream_t stream, bool need_host_out, int* slot_used) {
     const DevCorpus& dc = c->dc;
     const int B = (int)qs.size();
     const int64_t N = dc.N, U = dc.U;
@@ -200,33 +229,43 @@ int run_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_qu
         max_iters = std::max(max_iters, q.iters);
         max_m = std::max(max_m, q.m);
     }
+    if (opt.tile >= 0 && !sinkhorn_shape_fits(opt.tile, max_m, 1))
+        return fail(WMD_EINVAL, "options: tile %d cannot hold a %d-word query", opt.tile, max_m);
     const int per_launch = opt.iters_per_launch > 0 ? opt.iters_per_launch : INT_MAX;
     const bool chunked = per_launch < max_iters;
     const size_t kfloats = (size_t)U * sum_ldk;
     const size_t xfloats = chunked ? (size_t)N * sum_ldk : 0;
-    // parameter block: QueryDev[B] | qlist[B] | qid[sum_m] | r[sum_m] | rinv[sum_m]
+    // distance-kernel groups: contiguous runs of queries with balanced column counts,
+    // enough of them that row tiles x groups fills the device
+    const int64_t row_tiles = (U + 63) / 64;
+    const int G = (int)std::max<int64_t>(1, std::min<int64_t>(B, (2048 + row_tiles - 1) / row_tiles));
+    // parameter block: QueryDev[B] | qlist[B] | qgroup[G+1] | qid[sum_m] | r[sum_m] | rinv[sum_m]
     const size_t off_ql = align_up(sizeof(QueryDev) * B, 256);
-    const size_t off_id = align_up(off_ql + sizeof(int32_t) * B, 256);
+    const size_t off_qg = align_up(off_ql + sizeof(int32_t) * B, 256);
+    const size_t off_id = align_up(off_qg + sizeof(int32_t) * (G + 1), 256);
     const size_t off_r = align_up(off_id + sizeof(int32_t) * sum_m, 256);
     const size_t off_ri = align_up(off_r + sizeof(float) * sum_m, 256);
     const size_t pbytes = align_up(off_ri + sizeof(float) * sum_m, 256);
     const size_t obytes = need_host_out ? sizeof(double) * (size_t)B * N * (dev_res ? 2 : 1) : 0;
-    int rc = ensure_workspace(c, kfloats, xfloats, pbytes, obytes, need_host_out);
+    const size_t nfloats = opt.log_domain ? (size_t)U * B : 0;
+    const int wslot = c->next_ws;
+    c->next_ws = (c->next_ws + 1) % kWorkSlots;
+    Workspace& w = c->ws[wslot];
+    *slot_used = wslot;
+    int rc = ensure_workspace(w, kfloats, xfloats, nfloats, pbytes, obytes, need_host_out);
     if (rc) return rc;
-    Workspace& w = c->ws;
     if (need_host_out) {
         dev_out = w.out;
         if (dev_res) dev_res = w.out + (size_t)B * N;
     }
 
-    if (c->staging_valid) {
-        hipError_t e = hipEventSynchronize(c->staging_free);
-        if (e != hipSuccess) return hip_fail(e, "query: wait for staging area");
-    }
-    char* hp = w.h_params;
+    int slot_s = 0;
+    if ((rc = take_staging(c, pbytes, &slot_s))) return rc;
+    char* hp = c->stage.h[slot_s];
     char* dp = w.params;
     QueryDev* hq = reinterpret_cast<QueryDev*>(hp);
     int32_t* hql = reinterpret_cast<int32_t*>(hp + off_ql);
+    int32_t* hqg = reinterpret_cast<int32_t*>(hp + off_qg);
     int32_t* hid = reinterpret_cast<int32_t*>(hp + off_id);
     float* hr = reinterpret_cast<float*>(hp + off_r);
     float* hri = reinterpret_cast<float*>(hp + off_ri);
@@ -250,18 +289,34 @@ int run_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_qu
         d.ldk = q.ldk;
         d.iters = q.iters;
         d.shift = opt.log_domain ? 1 : 0;
+        d.nrow = opt.log_domain ? w.nrow + (size_t)U * b : nullptr;
+        d.km_from_k = q.lambda >= kKmFromKMinLambda ? 1 : 0;
+        d.inv_lambda = d.km_from_k ? 1.0f / q.lambda : 0.f;
         std::memcpy(hid + mo, q.ids.data(), sizeof(int32_t) * q.m);
         std::memcpy(hr + mo, q.r.data(), sizeof(float) * q.m);
         std::memcpy(hri + mo, q.rinv.data(), sizeof(float) * q.m);
         ko += q.ldk;
         mo += q.m;
     }
+    {
+        hqg[0] = 0;
+        int g = 1;
+        size_t acc = 0;
+        for (int b = 0; b < B && g < G; ++b) {
+            acc += qs[b].ldk;
+            if (acc * G >= sum_ldk * g && B - (b + 1) >= G - g) hqg[g++] = b + 1;
+        }
+        while (g < G) { hqg[g] = hqg[g - 1] + 1; ++g; }   // not reached when B >= G
+        hqg[G] = B;
+    }
     // group queries by Sinkhorn launch shape: streaming-only first, then each register shape
     std::vector<int> shape_of(B);
-    const int nshape = 8;
+    const int nshape = sinkhorn_num_shapes();
     std::vector<int> cnt(nshape + 1, 0);
     for (int b = 0; b < B; ++b) {
-        shape_of[b] = sinkhorn_shape_for(qs[b].m, kTileMaxDoc);
+        if (opt.tile == -2) shape_of[b] = -1;
+        else if (opt.tile >= 0) shape_of[b] = opt.tile;
+        else shape_of[b] = sinkhorn_shape_for(qs[b].m, kTileMaxDoc);
         cnt[shape_of[b] + 1]++;
     }
     std::vector<int> start(nshape + 2, 0);
@@ -272,12 +327,12 @@ int run_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_qu
     }
 
     hipError_t e;
-    if (c->done_valid && (e = hipStreamWaitEvent(stream, c->done, 0)) != hipSuccess)
-        return hip_fail(e, "query: order after previous call");
+    if (w.done_valid && (e = hipStreamWaitEvent(stream, w.done, 0)) != hipSuccess)
+        return hip_fail(e, "query: order after the slot's previous call");
     if ((e = hipMemcpyAsync(dp, hp, pbytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
         return hip_fail(e, "query: upload parameters");
-    if ((e = hipEventRecord(c->staging_free, stream)) != hipSuccess) return hip_fail(e, "query: record");
-    c->staging_valid = true;
+    if ((e = hipEventRecord(c->stage.ev[slot_s], stream)) != hipSuccess) return hip_fail(e, "query: record");
+    c->stage.pending[slot_s] = true;
 
     const QueryDev* dq = reinterpret_cast<const QueryDev*>(dp);
     const int32_t* dql = reinterpret_cast<const int32_t*>(dp + off_ql);
@@ -289,7 +344,8 @@ int run_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_qu
         if (c->slot_pending[slot] && (rc = fold_timing_slot(c, slot))) return rc;
         (void)hipEventRecord(c->ev[slot][0], stream);
     }
-    if ((e = launch_dist(dc, dq, B, max_m, opt.precision == WMD_DIST_BF16, stream)) != hipSuccess)
+    const int32_t* dqg = reinterpret_cast<const int32_t*>(dp + off_qg);
+    if ((e = launch_dist(dc, dq, dqg, G, opt.precision == WMD_DIST_BF16, stream)) != hipSuccess)
         return hip_fail(e, "query: distance kernel launch");
     ++launches;
     if (slot >= 0) (void)hipEventRecord(c->ev[slot][1], stream);
@@ -331,8 +387,8 @@ int run_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_qu
         c->last_slot = slot;
     }
     c->last_launches = launches;
-    if ((e = hipEventRecord(c->done, stream)) != hipSuccess) return hip_fail(e, "query: record");
-    c->done_valid = true;
+    if ((e = hipEventRecord(w.done, stream)) != hipSuccess) return hip_fail(e, "query: record");
+    w.done_valid = true;
     return WMD_OK;
 }
 
@@ -358,6 +414,7 @@ void wmd_query_options_init(wmd_query_options* opt) {
     opt->recompute_below = -1.f;
     opt->log_domain = 0;
     opt->iters_per_launch = 0;
+    opt->tile = -1;
 }
 
 static void corpus_free(wmd_corpus* c) {
@@ -372,19 +429,24 @@ static void corpus_free(wmd_corpus* c) {
     dfree(d.scol);
     dfree(d.scw);
     dfree(d.sdoc);
-    Workspace& w = c->ws;
-    dfree(w.Kt);
-    dfree(w.KMt);
-    dfree(w.x);
-    dfree(w.params);
-    dfree(w.out);
-    hfree(w.h_params);
-    hfree(w.h_out);
+    for (int sl = 0; sl < kWorkSlots; ++sl) {
+        Workspace& w = c->ws[sl];
+        dfree(w.Kt);
+        dfree(w.KMt);
+        dfree(w.x);
+        dfree(w.nrow);
+        dfree(w.params);
+        dfree(w.out);
+        hfree(w.h_out);
+        if (w.done) (void)hipEventDestroy(w.done);
+    }
+    for (int i = 0; i < Staging::kSlots; ++i) {
+        hfree(c->stage.h[i]);
+        if (c->stage.ev[i]) (void)hipEventDestroy(c->stage.ev[i]);
+    }
     for (int i = 0; i < wmd_corpus::kTimingSlots; ++i)
         for (int j = 0; j < 3; ++j)
             if (c->ev[i][j]) (void)hipEventDestroy(c->ev[i][j]);
-    if (c->done) (void)hipEventDestroy(c->done);
-    if (c->staging_free) (void)hipEventDestroy(c->staging_free);
     if (c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -489,9 +551,12 @@ int wmd_corpus_create(const float* vecs, int64_t V, int32_t dim, const int64_t* 
         return code;
     };
     if ((e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess) return bail(e, "corpus: stream");
-    if ((e = hipEventCreateWithFlags(&c->done, hipEventDisableTiming)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&c->staging_free, hipEventDisableTiming)) != hipSuccess)
-        return bail(e, "corpus: events");
+    for (int sl = 0; sl < kWorkSlots; ++sl)
+        if ((e = hipEventCreateWithFlags(&c->ws[sl].done, hipEventDisableTiming)) != hipSuccess)
+            return bail(e, "corpus: events");
+    for (int i = 0; i < Staging::kSlots; ++i)
+        if ((e = hipEventCreateWithFlags(&c->stage.ev[i], hipEventDisableTiming)) != hipSuccess)
+            return bail(e, "corpus: events");
     for (int i = 0; i < wmd_corpus::kTimingSlots; ++i)
         for (int j = 0; j < 3; ++j)
             if ((e = hipEventCreate(&c->ev[i][j])) != hipSuccess) return bail(e, "corpus: timing events");
@@ -534,7 +599,8 @@ void wmd_corpus_destroy(wmd_corpus* c) {
     if (!c) return;
     DeviceGuard guard(c->dc.device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    if (c->done_valid) (void)hipEventSynchronize(c->done);
+    for (int sl = 0; sl < kWorkSlots; ++sl)
+        if (c->ws[sl].done_valid) (void)hipEventSynchronize(c->ws[sl].done);
     corpus_free(c);
 }
 
@@ -559,6 +625,8 @@ static int check_opts(const wmd_query_options* in, wmd_query_options* o) {
         return fail(WMD_EINVAL, "options: unknown precision %d", o->precision);
     if (!std::isfinite(o->recompute_below)) return fail(WMD_EINVAL, "options: recompute_below not finite");
     if (o->iters_per_launch < 0) return fail(WMD_EINVAL, "options: iters_per_launch < 0");
+    if (o->tile < -2 || o->tile >= sinkhorn_num_shapes())
+        return fail(WMD_EINVAL, "options: tile %d outside [-2, %d)", o->tile, sinkhorn_num_shapes());
     return WMD_OK;
 }
 
@@ -581,14 +649,14 @@ static int batch_plan(wmd_corpus* c, int32_t B, const int64_t* q_ptr, const int3
     return WMD_OK;
 }
 
-static int finish_sync(wmd_corpus* c, int B, double* out_dist, double* out_resid) {
-    Workspace& w = c->ws;
+static int finish_sync(wmd_corpus* c, int slot, int B, double* out_dist, double* out_resid) {
+    Workspace& w = c->ws[slot];
     const size_t n = (size_t)B * c->dc.N;
     const size_t bytes = sizeof(double) * n * (out_resid ? 2 : 1);
     hipError_t e;
     if ((e = hipMemcpyAsync(w.h_out, w.out, bytes, hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
         return hip_fail(e, "query: download results");
-    if ((e = hipEventRecord(c->done, c->stream)) != hipSuccess) return hip_fail(e, "query: record");
+    if ((e = hipEventRecord(w.done, c->stream)) != hipSuccess) return hip_fail(e, "query: record");
     if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(e, "query: execution");
     std::memcpy(out_dist, w.h_out, sizeof(double) * n);
     if (out_resid) std::memcpy(out_resid, w.h_out + n, sizeof(double) * n);
@@ -607,8 +675,9 @@ int wmd_query(wmd_corpus* c, const int32_t* qids, const float* qweights, int32_t
     DeviceGuard guard(c->dc.device);
     if (!guard.ok()) return fail(WMD_EDEVICE, "query: cannot select device");
     double dummy = 0.0;
-    if ((rc = run_queries(c, qs, o, &dummy, out_resid ? &dummy : nullptr, c->stream, true))) return rc;
-    return finish_sync(c, 1, out_dist, out_resid);
+    int slot = 0;
+    if ((rc = run_queries(c, qs, o, &dummy, out_resid ? &dummy : nullptr, c->stream, true, &slot))) return rc;
+    return finish_sync(c, slot, 1, out_dist, out_resid);
 }
 
 int wmd_query_async(wmd_corpus* c, const int32_t* qids, const float* qweights, int32_t n, float lambda,
@@ -623,7 +692,8 @@ int wmd_query_async(wmd_corpus* c, const int32_t* qids, const float* qweights, i
     std::lock_guard<std::mutex> lk(c->mu);
     DeviceGuard guard(c->dc.device);
     if (!guard.ok()) return fail(WMD_EDEVICE, "query: cannot select device");
-    return run_queries(c, qs, o, dev_dist, dev_resid, (hipStream_t)stream, false);
+    int slot = 0;
+    return run_queries(c, qs, o, dev_dist, dev_resid, (hipStream_t)stream, false, &slot);
 }
 
 int wmd_query_batch(wmd_corpus* c, int32_t B, const int64_t* q_ptr, const int32_t* qids, const float* qweights,
@@ -639,8 +709,9 @@ int wmd_query_batch(wmd_corpus* c, int32_t B, const int64_t* q_ptr, const int32_
     DeviceGuard guard(c->dc.device);
     if (!guard.ok()) return fail(WMD_EDEVICE, "batch: cannot select device");
     double dummy = 0.0;
-    if ((rc = run_queries(c, qs, o, &dummy, out_resid ? &dummy : nullptr, c->stream, true))) return rc;
-    return finish_sync(c, B, out_dist, out_resid);
+    int slot = 0;
+    if ((rc = run_queries(c, qs, o, &dummy, out_resid ? &dummy : nullptr, c->stream, true, &slot))) return rc;
+    return finish_sync(c, slot, B, out_dist, out_resid);
 }
 
 int wmd_query_batch_async(wmd_corpus* c, int32_t B, const int64_t* q_ptr, const int32_t* qids,
@@ -655,7 +726,8 @@ int wmd_query_batch_async(wmd_corpus* c, int32_t B, const int64_t* q_ptr, const 
     std::lock_guard<std::mutex> lk(c->mu);
     DeviceGuard guard(c->dc.device);
     if (!guard.ok()) return fail(WMD_EDEVICE, "batch: cannot select device");
-    return run_queries(c, qs, o, dev_dist, dev_resid, (hipStream_t)stream, false);
+    int slot = 0;
+    return run_queries(c, qs, o, dev_dist, dev_resid, (hipStream_t)stream, false, &slot);
 }
 
 int wmd_set_timing(wmd_corpus* c, int32_t enable) {

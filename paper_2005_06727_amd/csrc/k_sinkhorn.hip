@@ -17,8 +17,12 @@
 //   s_i   = sum_k A[i][k] u_k            (partial over q, then summed over b)
 //   v_i   = c_i / s_i                    (rows; every b holds a copy)
 //   x_k   = (1 / r_k) sum_i A[i][k] v_i  (partial over p, then summed over a)
-// Final: u = 1/x, v = c / (A u), WMD = sum_{i,k} (KMt[i][k] u_k) v_i with the
-// products in FP32 and the sum in FP64; optionally the FP64 residual
+// Final: u = 1/x, v = c / (A u), WMD = sum_{i,k} ((K .* M)[i][k] u_k) v_i with
+// the products in FP32 and the sum in FP64, where K .* M is rebuilt from the
+// K block already in registers (M = n_i - ln K / lambda, n_i the row's
+// log-domain shift or 0) for lambda >= 0.5, else gathered from KMt; the
+// absolute error of the rebuilt M is about ulp(lambda M) / lambda, so its
+// relative error stays at FP32 rounding level.  Optionally the FP64 residual
 // sum_k |u_k (A^T v)_k - r_k| of the plan's row marginal (its column marginal
 // is c by construction).
 #include "wmd_internal.h"
@@ -32,16 +36,28 @@ __device__ __forceinline__ float dpp(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
 }
 
-__device__ __forceinline__ float swz_xor16(float v) {
-    // ds_swizzle bit mode: and 0x1f, or 0, xor 0x10 -> lane ^ 16 within 32 lanes
-    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
+// lane ^ 16 and lane ^ 32 partner sums with the gfx950 row-swap VALU ops:
+// with both operands = v, the two results hold v of this lane and of its
+// partner, in the same order on both lanes, so both get identical bits.
+__device__ __forceinline__ float add_xor16(float v) {
+    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-__device__ __forceinline__ float shfl_xor32(float v) {
-    return __shfl_xor(v, 32, 64);
+__device__ __forceinline__ float add_xor32(float v) {
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-// Sum over the C consecutive lanes (C a power of two <= 16) sharing a team row.
+// lane ^ 4 within each 16-lane row: row_shl:4 into banks 0 and 2 (lanes 0-3,
+// 8-11), row_shr:4 into banks 1 and 3.
+__device__ __forceinline__ float xor4(float v) {
+    const int i = __float_as_int(v);
+    int t = __builtin_amdgcn_update_dpp(i, i, 0x104, 0xF, 0x5, false);
+    t = __builtin_amdgcn_update_dpp(t, i, 0x114, 0xF, 0xA, false);
+    return __int_as_float(t);
+}
+
 template <int C>
 __device__ __forceinline__ float sum_over_b(float v) {
     if constexpr (C >= 2) v += dpp<0xB1>(v);    // quad_perm [1,0,3,2]: lane ^ 1
@@ -51,23 +67,18 @@ __device__ __forceinline__ float sum_over_b(float v) {
     return v;
 }
 
-__device__ __forceinline__ float swz_xor4(float v) {
-    // ds_swizzle bit mode: and 0x1f, or 0, xor 0x04 -> lane ^ 4 within 32 lanes
-    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x101F));
-}
-
 // Sum over the R lanes with the same b (lane stride C) of an R*C-lane team.
-// Every step pairs lane l with lane l ^ o, so all R lanes end with the same
-// bits (a + b == b + a): the R copies of x stay identical.
+// Every step pairs lane l with lane l ^ o; IEEE addition is commutative, so
+// both partners get the same bits and the R copies of x stay identical.
 template <int R, int C>
 __device__ __forceinline__ float sum_over_a(float v) {
     constexpr int T = R * C;
     if constexpr (C <= 1 && T > 1) v += dpp<0xB1>(v);    // lane ^ 1
     if constexpr (C <= 2 && T > 2) v += dpp<0x4E>(v);    // lane ^ 2
-    if constexpr (C <= 4 && T > 4) v += swz_xor4(v);     // lane ^ 4
+    if constexpr (C <= 4 && T > 4) v += xor4(v);         // lane ^ 4
     if constexpr (C <= 8 && T > 8) v += dpp<0x128>(v);   // row_ror:8 == lane ^ 8 within a row
-    if constexpr (T > 16) v += swz_xor16(v);             // lane ^ 16
-    if constexpr (T > 32) v += shfl_xor32(v);            // lane ^ 32
+    if constexpr (T > 16) v = add_xor16(v);              // lane ^ 16
+    if constexpr (T > 32) v = add_xor32(v);              // lane ^ 32
     return v;
 }
 
@@ -120,32 +131,38 @@ __global__ __launch_bounds__(256) void k_sink(SinkArgs g) {
     const int n = valid ? g.sptr[d + 1] - rs : 0;
     const int kb = (wi * C + b) * Q;
 
-    const int pn_w = wave_max((n + R - 1) / R);                        // row blocks in use (wave)
-    const int qb_w = wave_max((min(max(m - kb, 0), Q) + 3) >> 2);      // float4 column blocks in use
+    // row blocks in use, uniform over the wave (documents of a launch are sorted
+    // by length, so the teams of a wave have similar n); held in an SGPR
+    const int pn = __builtin_amdgcn_readfirstlane(wave_max((n + R - 1) / R));
 
+    // A and every per-column / per-row vector are zero outside the document's
+    // n x m block, so the arithmetic below needs no per-element guards
     float A[P][Q];
     float cval[P];
-    // load the document's block of Kt (and its weights) once
+    bool kval[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) kval[q] = kb + q < m;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         cval[p] = 0.f;
 #pragma unroll
         for (int q = 0; q < Q; ++q) A[p][q] = 0.f;
-        if (p < pn_w) {
-            const int i = a + R * p;
-            if (i < n) {
-                cval[p] = g.scw[rs + i];
-                const float* row = qp->Kt + (int64_t)g.scol[rs + i] * ldk;
+    }
 #pragma unroll
-                for (int q4 = 0; q4 < Q4; ++q4) {
-                    const int k0 = kb + 4 * q4;
-                    if (q4 < qb_w && k0 < m) {
-                        float4 t = *reinterpret_cast<const float4*>(row + k0);
-                        A[p][4 * q4 + 0] = t.x;
-                        A[p][4 * q4 + 1] = (k0 + 1 < m) ? t.y : 0.f;
-                        A[p][4 * q4 + 2] = (k0 + 2 < m) ? t.z : 0.f;
-                        A[p][4 * q4 + 3] = (k0 + 3 < m) ? t.w : 0.f;
-                    }
+    for (int p = 0; p < P; ++p) {
+        const int i = a + R * p;
+        if (p < pn && i < n) {
+            cval[p] = g.scw[rs + i];
+            const float* row = qp->Kt + (int64_t)g.scol[rs + i] * ldk;
+#pragma unroll
+            for (int q4 = 0; q4 < Q4; ++q4) {
+                const int k0 = kb + 4 * q4;
+                if (k0 < m) {
+                    float4 t = *reinterpret_cast<const float4*>(row + k0);
+                    A[p][4 * q4 + 0] = t.x;
+                    A[p][4 * q4 + 1] = kval[4 * q4 + 1] ? t.y : 0.f;
+                    A[p][4 * q4 + 2] = kval[4 * q4 + 2] ? t.z : 0.f;
+                    A[p][4 * q4 + 3] = kval[4 * q4 + 3] ? t.w : 0.f;
                 }
             }
         }
@@ -155,10 +172,9 @@ __global__ __launch_bounds__(256) void k_sink(SinkArgs g) {
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int k = kb + q;
-        const bool kv = k < m;
-        rinv[q] = kv ? qp->rinv[k] : 0.f;
-        if (g.it_begin == 0) x[q] = kv ? 1.0f / (float)m : 1.f;
-        else x[q] = kv ? qp->x[(int64_t)d * ldk + k] : 1.f;
+        rinv[q] = kval[q] ? qp->rinv[k] : 0.f;
+        if (g.it_begin == 0) x[q] = kval[q] ? 1.0f / (float)m : 1.f;
+        else x[q] = kval[q] ? qp->x[(int64_t)d * ldk + k] : 1.f;
     }
 
     int it_end = valid ? min(g.it_begin + g.it_count, qp->iters) : g.it_begin;
@@ -180,29 +196,31 @@ __global__ __launch_bounds__(256) void k_sink(SinkArgs g) {
     for (int p = 0; p < P; ++p) s[p] = 0.f;
     int par = 0;
 
-    // s = A u summed over the whole team (lanes b, then waves)
+    // s = A u summed over the team (lanes b, then waves); v = c / s
     auto sddmm = [&](void) {
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            if (p < pn_w) {
+            if (p < pn) {
                 float acc = 0.f;
 #pragma unroll
-                for (int q = 0; q < Q; ++q)
-                    if (q / 4 < qb_w) acc = fmaf(A[p][q], u[q], acc);
-                s[p] = sum_over_b<C>(acc);
+                for (int q = 0; q < Q; ++q) acc = fmaf(A[p][q], u[q], acc);
+                s[p] = acc;
             }
         }
+        // rows p >= pn hold zeros; reducing them too lets the reductions interleave
+#pragma unroll
+        for (int p = 0; p < P; ++p) s[p] = sum_over_b<C>(s[p]);
         if constexpr (W > 1) {
             float* sp = s_part + ((team * 2 + par) * W) * (R * P);
             if (b == 0) {
 #pragma unroll
                 for (int p = 0; p < P; ++p)
-                    if (p < pn_w) sp[wi * R * P + a + R * p] = s[p];
+                    if (p < pn) sp[wi * R * P + a + R * p] = s[p];
             }
             __syncthreads();
 #pragma unroll
             for (int p = 0; p < P; ++p) {
-                if (p < pn_w) {
+                if (p < pn) {
                     float t = 0.f;
                     for (int w2 = 0; w2 < W; ++w2) t += sp[w2 * R * P + a + R * p];
                     s[p] = t;
@@ -214,22 +232,31 @@ __global__ __launch_bounds__(256) void k_sink(SinkArgs g) {
         for (int p = 0; p < P; ++p) v[p] = (cval[p] > 0.f) ? cval[p] * rcp(s[p]) : 0.f;
     };
 
+    // y = A^T v summed over the team's rows (lanes a)
+    float y[Q];
+    auto spmm = [&](void) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) y[q] = 0.f;
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            if (p < pn) {
+#pragma unroll
+                for (int q = 0; q < Q; ++q) y[q] = fmaf(A[p][q], v[p], y[q]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) y[q] = sum_over_a<R, C>(y[q]);
+    };
+
     for (int it = g.it_begin; it < it_end; ++it) {
         const bool act = it < my_end;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) u[q] = (act && kb + q < m) ? rcp(x[q]) : 0.f;
+        for (int q = 0; q < Q; ++q) u[q] = (act && kval[q]) ? rcp(x[q]) : 0.f;
         sddmm();
+        spmm();
         if (act) {
 #pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                if (q / 4 < qb_w) {
-                    float acc = 0.f;
-#pragma unroll
-                    for (int p = 0; p < P; ++p)
-                        if (p < pn_w) acc = fmaf(A[p][q], v[p], acc);
-                    x[q] = sum_over_a<R, C>(acc) * rinv[q];
-                }
-            }
+            for (int q = 0; q < Q; ++q) x[q] = y[q] * rinv[q];
         }
     }
 
@@ -244,44 +271,57 @@ __global__ __launch_bounds__(256) void k_sink(SinkArgs g) {
 
     // final step: u = 1/x, v = c / (K^T u)
 #pragma unroll
-    for (int q = 0; q < Q; ++q) u[q] = (kb + q < m) ? rcp(x[q]) : 0.f;
+    for (int q = 0; q < Q; ++q) u[q] = kval[q] ? rcp(x[q]) : 0.f;
     sddmm();
 
     double rho = 0.0;
     const bool want_resid = valid && qp->resid != nullptr;
-    if (want_resid) {
+    if (__builtin_amdgcn_readfirstlane((int)(qp->resid != nullptr))) {
+        spmm();
+        if (want_resid && a == 0) {
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            if (q / 4 < qb_w) {
-                float acc = 0.f;
-#pragma unroll
-                for (int p = 0; p < P; ++p)
-                    if (p < pn_w) acc = fmaf(A[p][q], v[p], acc);
-                const float y = sum_over_a<R, C>(acc);
-                if (a == 0 && kb + q < m)
-                    rho += fabs((double)u[q] * (double)y - (double)qp->r[kb + q]);
-            }
+            for (int q = 0; q < Q; ++q)
+                if (kval[q]) rho += fabs((double)u[q] * (double)y[q] - (double)qp->r[kb + q]);
         }
     }
 
-    // WMD = sum_i v_i sum_k KMt[i][k] u_k
+    // WMD = sum_i v_i sum_k (K .* M)[i][k] u_k: FP32 products, FP64 sum.  K .* M
+    // is rebuilt from the K block in registers (M = n_i - ln K / lambda) or
+    // gathered from KMt when lambda is too small for that.
     double wsum = 0.0;
+    if (qp->km_from_k) {
+        const float il = qp->inv_lambda;
 #pragma unroll
-    for (int p = 0; p < P; ++p) {
-        if (p < pn_w) {
+        for (int p = 0; p < P; ++p) {
+            if (p < pn) {
+                const int i = a + R * p;
+                const float nr = (qp->nrow && i < n) ? qp->nrow[g.scol[rs + i]] : 0.f;
+                const double vp = (double)v[p];
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const float kk = A[p][q];
+                    const float km = (kk > 0.f) ? kk * (nr - logf(kk) * il) : 0.f;
+                    wsum = fma((double)(km * u[q]), vp, wsum);
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
             const int i = a + R * p;
-            if (i < n) {
+            if (p < pn && i < n) {
                 const float* row = qp->KMt + (int64_t)g.scol[rs + i] * ldk;
                 const double vp = (double)v[p];
 #pragma unroll
                 for (int q4 = 0; q4 < Q4; ++q4) {
                     const int k0 = kb + 4 * q4;
-                    if (q4 < qb_w && k0 < m) {
+                    if (k0 < m) {
                         float4 t = *reinterpret_cast<const float4*>(row + k0);
+                        // u is zero beyond m, so the padded columns add nothing
                         wsum = fma((double)(t.x * u[4 * q4 + 0]), vp, wsum);
-                        if (k0 + 1 < m) wsum = fma((double)(t.y * u[4 * q4 + 1]), vp, wsum);
-                        if (k0 + 2 < m) wsum = fma((double)(t.z * u[4 * q4 + 2]), vp, wsum);
-                        if (k0 + 3 < m) wsum = fma((double)(t.w * u[4 * q4 + 3]), vp, wsum);
+                        wsum = fma((double)(t.y * u[4 * q4 + 1]), vp, wsum);
+                        wsum = fma((double)(t.z * u[4 * q4 + 2]), vp, wsum);
+                        wsum = fma((double)(t.w * u[4 * q4 + 3]), vp, wsum);
                     }
                 }
             }
@@ -371,9 +411,20 @@ __global__ __launch_bounds__(256) void k_sink_stream(SinkArgs g) {
         }
     }
     for (int i = tid; i < n; i += 256) {
-        const float* row = qp->KMt + (int64_t)g.scol[rs + i] * ldk;
+        const int col = g.scol[rs + i];
         const double vi = (double)v[i];
-        for (int k = 0; k < m; ++k) wsum = fma((double)(row[k] * u[k]), vi, wsum);
+        if (qp->km_from_k) {   // K .* M rebuilt from K: M = n_i - ln K / lambda
+            const float* row = qp->Kt + (int64_t)col * ldk;
+            const float nr = qp->nrow ? qp->nrow[col] : 0.f, il = qp->inv_lambda;
+            for (int k = 0; k < m; ++k) {
+                const float kk = row[k];
+                const float km = (kk > 0.f) ? kk * (nr - logf(kk) * il) : 0.f;
+                wsum = fma((double)(km * u[k]), vi, wsum);
+            }
+        } else {
+            const float* row = qp->KMt + (int64_t)col * ldk;
+            for (int k = 0; k < m; ++k) wsum = fma((double)(row[k] * u[k]), vi, wsum);
+        }
     }
     wsum = team_sum_f64<64>(wsum);
     rho = team_sum_f64<64>(rho);
@@ -389,32 +440,219 @@ __global__ __launch_bounds__(256) void k_sink_stream(SinkArgs g) {
     }
 }
 
+// Row-lane form for short queries: one wave per (query, document).  Lane l
+// holds rows l + 64 r (r < RP) of the document's K block in registers, so the
+// SDDMM s_i = sum_k A[i][k] u_k is an in-lane dot product with u broadcast
+// from LDS.  The block is also kept transposed in LDS, and for the SpMM lane l
+// owns column l % MQ and sums part l / MQ of the rows, so neither phase needs
+// cross-lane reductions; the H = 64 / MQ row parts are combined with lane
+// swaps.  One reciprocal per lane and row / column per iteration.
+template <int MQ, int RP>
+__global__ __launch_bounds__(64) void k_sink_rows(SinkArgs g) {
+    constexpr int H = 64 / MQ;              // row parts in the SpMM
+    constexpr int NR = 64 * RP;             // rows held by the wave
+    constexpr int LDT = NR + 4;             // transposed block row stride (floats)
+    constexpr int MQ4 = MQ / 4;
+    static_assert(H == 1 || H == 2 || H == 4, "MQ in {16, 32, 64}");
+    __shared__ __attribute__((aligned(16))) float At[MQ * LDT];
+    __shared__ __attribute__((aligned(16))) float uS[MQ];
+    __shared__ __attribute__((aligned(16))) float vS[NR];
+    __shared__ double red[2];
+
+    const int lane = threadIdx.x;
+    const int64_t item = blockIdx.x;
+    const int nd = g.d_end - g.d_begin;
+    const int qidx = g.qlist[item / nd];
+    const int d = g.d_begin + (int)(item % nd);
+    const QueryDev* qp = g.qd + qidx;
+    const int m = qp->m, ldk = qp->ldk;
+    const int rs = g.sptr[d];
+    const int n = g.sptr[d + 1] - rs;
+
+    // rows: registers and the transposed LDS copy (zeros outside n x m)
+    float A[RP][MQ];
+    float cval[RP];
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+        const int i = lane + 64 * r;
+        cval[r] = 0.f;
+#pragma unroll
+        for (int k = 0; k < MQ; ++k) A[r][k] = 0.f;
+        if (i < n) {
+            cval[r] = g.scw[rs + i];
+            const float* row = qp->Kt + (int64_t)g.scol[rs + i] * ldk;
+#pragma unroll
+            for (int k4 = 0; k4 < MQ4; ++k4) {
+                if (4 * k4 < m) {
+                    const float4 t = *reinterpret_cast<const float4*>(row + 4 * k4);
+                    A[r][4 * k4 + 0] = t.x;
+                    A[r][4 * k4 + 1] = (4 * k4 + 1 < m) ? t.y : 0.f;
+                    A[r][4 * k4 + 2] = (4 * k4 + 2 < m) ? t.z : 0.f;
+                    A[r][4 * k4 + 3] = (4 * k4 + 3 < m) ? t.w : 0.f;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < MQ; ++k) At[k * LDT + i] = A[r][k];
+    }
+
+    // SpMM lane roles: column kc, rows [i0, i1) in steps of 4
+    const int kc = lane % MQ, h = lane / MQ;
+    const bool kv = kc < m;
+    const int n4 = (n + 3) & ~3;
+    const int part = (((n4 / 4) + H - 1) / H) * 4;
+    const int i0 = min(h * part, n4), i1 = min(i0 + part, n4);
+    const float rinv = kv ? qp->rinv[kc] : 0.f;
+    float x = kv ? 1.0f / (float)m : 1.f;
+    if (g.it_begin > 0 && kv) x = qp->x[(int64_t)d * ldk + kc];
+    float u = 0.f, v[RP];
+
+    auto sddmm = [&](void) {
+        if (h == 0) uS[kc] = u;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RP; ++r) {
+            float acc = 0.f;
+#pragma unroll
+            for (int k4 = 0; k4 < MQ4; ++k4) {
+                const float4 uu = *reinterpret_cast<const float4*>(&uS[4 * k4]);
+                acc = fmaf(A[r][4 * k4 + 0], uu.x, acc);
+                acc = fmaf(A[r][4 * k4 + 1], uu.y, acc);
+                acc = fmaf(A[r][4 * k4 + 2], uu.z, acc);
+                acc = fmaf(A[r][4 * k4 + 3], uu.w, acc);
+            }
+            v[r] = (cval[r] > 0.f) ? cval[r] * rcp(acc) : 0.f;
+            vS[lane + 64 * r] = v[r];
+        }
+        __syncthreads();
+    };
+    // y_kc = sum_i At[kc][i] v_i over this lane's row part, then over the parts
+    auto spmm = [&](void) -> float {
+        float y = 0.f;
+        const float* at = &At[kc * LDT];
+        for (int i = i0; i < i1; i += 4) {
+            const float4 a4 = *reinterpret_cast<const float4*>(at + i);
+            const float4 v4 = *reinterpret_cast<const float4*>(&vS[i]);
+            y = fmaf(a4.x, v4.x, y);
+            y = fmaf(a4.y, v4.y, y);
+            y = fmaf(a4.z, v4.z, y);
+            y = fmaf(a4.w, v4.w, y);
+        }
+        if constexpr (H >= 4) y = add_xor16(y);
+        if constexpr (H >= 2) y = add_xor32(y);
+        return y;
+    };
+
+    const int it_end = min(g.it_begin + g.it_count, qp->iters);
+    for (int it = g.it_begin; it < it_end; ++it) {
+        u = kv ? rcp(x) : 0.f;
+        sddmm();
+        x = spmm() * rinv;
+    }
+    if (!g.final_step) {
+        if (h == 0 && kv) qp->x[(int64_t)d * ldk + kc] = x;
+        return;
+    }
+    u = kv ? rcp(x) : 0.f;
+    sddmm();
+    double rho = 0.0;
+    if (qp->resid) {
+        const float y = spmm();
+        if (h == 0 && kv) rho = fabs((double)u * (double)y - (double)qp->r[kc]);
+    }
+    // WMD = sum_i v_i sum_k (K .* M)[i][k] u_k: FP32 products, FP64 sum; K .* M
+    // rebuilt from the registers (M = n_i - ln K / lambda) or gathered from KMt
+    double wsum = 0.0;
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+        const int i = lane + 64 * r;
+        if (i < n) {
+            const double vr = (double)v[r];
+            if (qp->km_from_k) {
+                const float il = qp->inv_lambda;
+                const float nr = qp->nrow ? qp->nrow[g.scol[rs + i]] : 0.f;
+#pragma unroll
+                for (int k4 = 0; k4 < MQ4; ++k4) {
+                    const float4 uu = *reinterpret_cast<const float4*>(&uS[4 * k4]);
+                    const float ue[4] = {uu.x, uu.y, uu.z, uu.w};
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const float kk = A[r][4 * k4 + e];
+                        const float km = (kk > 0.f) ? kk * (nr - logf(kk) * il) : 0.f;
+                        wsum = fma((double)(km * ue[e]), vr, wsum);
+                    }
+                }
+            } else {
+                const float* row = qp->KMt + (int64_t)g.scol[rs + i] * ldk;
+#pragma unroll
+                for (int k4 = 0; k4 < MQ4; ++k4) {
+                    if (4 * k4 < m) {
+                        const float4 t = *reinterpret_cast<const float4*>(row + 4 * k4);
+                        const float4 uu = *reinterpret_cast<const float4*>(&uS[4 * k4]);
+                        // uS is zero past m, so the padded columns add nothing
+                        wsum = fma((double)(t.x * uu.x), vr, wsum);
+                        wsum = fma((double)(t.y * uu.y), vr, wsum);
+                        wsum = fma((double)(t.z * uu.z), vr, wsum);
+                        wsum = fma((double)(t.w * uu.w), vr, wsum);
+                    }
+                }
+            }
+        }
+    }
+    wsum = team_sum_f64<64>(wsum);
+    rho = team_sum_f64<64>(rho);
+    (void)red;
+    if (lane == 0) {
+        const int doc = g.sdoc[d];
+        qp->out[doc] = wsum;
+        if (qp->resid) qp->resid[doc] = rho;
+    }
+}
+
 struct Shape {
-    int max_m, max_n, teams_per_block;
+    int max_m, max_n, teams_per_block, threads;
     void (*kern)(SinkArgs);
 };
 
 template <int R, int C, int P, int Q, int W>
 constexpr Shape make_shape() {
-    return Shape{C * Q * W, R * P, (W == 1) ? 4 * (64 / (R * C)) : 4 / W, &k_sink<R, C, P, Q, W>};
+    return Shape{C * Q * W, R * P, (W == 1) ? 4 * (64 / (R * C)) : 4 / W, 256, &k_sink<R, C, P, Q, W>};
+}
+
+template <int MQ, int RP>
+constexpr Shape make_rows_shape() {
+    return Shape{MQ, 64 * RP, 1, 64, &k_sink_rows<MQ, RP>};
 }
 
 const Shape kShapes[] = {
     make_shape<4, 4, 16, 4, 1>(),    // 0: m <= 16,  16-lane teams
-    make_shape<8, 4, 8, 8, 1>(),     // 1: m <= 32,  32-lane teams
-    make_shape<8, 8, 8, 8, 1>(),     // 2: m <= 64,  one wave
-    make_shape<4, 16, 16, 8, 1>(),   // 3: m <= 128, one wave
-    make_shape<4, 16, 16, 8, 2>(),   // 4: m <= 256, two waves
-    make_shape<4, 16, 16, 8, 4>(),   // 5: m <= 512, four waves
+    make_shape<4, 4, 16, 8, 1>(),    // 1: m <= 32,  16-lane teams
+    make_shape<8, 4, 8, 8, 1>(),     // 2: m <= 32,  32-lane teams
+    make_shape<4, 8, 16, 8, 1>(),    // 3: m <= 64,  32-lane teams
+    make_shape<8, 8, 8, 8, 1>(),     // 4: m <= 64,  one wave
+    make_shape<4, 16, 16, 8, 1>(),   // 5: m <= 128, one wave
+    make_shape<4, 16, 16, 8, 2>(),   // 6: m <= 256, two waves
+    make_shape<4, 16, 16, 8, 4>(),   // 7: m <= 512, four waves
+    make_rows_shape<16, 1>(),        // 8: m <= 16,  row lanes
+    make_rows_shape<32, 1>(),        // 9: m <= 32,  row lanes
+    make_rows_shape<64, 1>(),        // 10: m <= 64, row lanes
 };
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+// default shape per query-length class (first entry whose max_m covers m)
+const int kDefaultShapes[] = {0, 2, 4, 5, 6, 7};
 
 }  // namespace
 
+int sinkhorn_num_shapes() { return kNumShapes; }
+
 int sinkhorn_shape_for(int m, int max_n) {
-    for (int s = 0; s < kNumShapes; ++s)
+    for (int s : kDefaultShapes)
         if (m <= kShapes[s].max_m && max_n <= kShapes[s].max_n) return s;
     return -1;
+}
+
+bool sinkhorn_shape_fits(int shape, int m, int max_n) {
+    return shape >= 0 && shape < kNumShapes && m <= kShapes[shape].max_m && max_n <= kShapes[shape].max_n;
 }
 
 int sinkhorn_shape_max_m(int shape) { return shape < 0 ? 4096 : kShapes[shape].max_m; }
@@ -436,7 +674,7 @@ hipError_t launch_sinkhorn(int shape, const SinkArgs& a, int max_m, int max_n, h
     }
     const Shape& sh = kShapes[shape];
     const int64_t blocks = (nitems + sh.teams_per_block - 1) / sh.teams_per_block;
-    hipLaunchKernelGGL(sh.kern, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(sh.kern, dim3((unsigned)blocks), dim3(sh.threads), 0, s, a);
     return hipGetLastError();
 }
 

@@ -15,20 +15,41 @@ namespace wmd {
 constexpr int kMaxQueryWords = 4096;   // streaming kernel LDS: 3 floats per query word
 constexpr int kMaxDocWords = 16384;    // streaming kernel LDS: 1 float per document word
 constexpr int kTileMaxDoc = 64;        // documents up to this length use the register tiles
+constexpr float kKmFromKMinLambda = 0.5f;  // from this lambda on, K .* M is rebuilt from K
 
+// Device buffers of one query call.  A corpus has kWorkSlots of them, used
+// round-robin, so a call can run while the previous one is still on the
+// device (when the two are on different streams); a slot is reused only after
+// its previous call's work has finished (event `done`, waited on the device).
 struct Workspace {
     float* Kt = nullptr;
     float* KMt = nullptr;
     size_t kcap = 0;          // floats in each of Kt, KMt
     float* x = nullptr;
     size_t xcap = 0;
+    float* nrow = nullptr;    // per-query log-domain row shifts (U each)
+    size_t ncap = 0;
     char* params = nullptr;   // device parameter block
-    char* h_params = nullptr; // pinned staging of the parameter block
     size_t pcap = 0;
     double* out = nullptr;    // device results of synchronous calls
     size_t ocap = 0;          // bytes
     double* h_out = nullptr;  // pinned copy of `out`
     size_t hocap = 0;
+    hipEvent_t done = nullptr;
+    bool done_valid = false;
+};
+constexpr int kWorkSlots = 2;
+
+// Pinned host staging of the parameter blocks: a ring, so the host can enqueue
+// several calls ahead of the device; slot i is reusable once its upload
+// (event ev[i]) has run.
+struct Staging {
+    static constexpr int kSlots = 8;
+    char* h[kSlots] = {};
+    hipEvent_t ev[kSlots] = {};
+    bool pending[kSlots] = {};
+    int next = 0;
+    size_t cap = 0;
 };
 
 struct PlannedQuery {
@@ -62,10 +83,6 @@ struct wmd_corpus {
     int64_t device_bytes = 0;
     std::mutex mu;
     hipStream_t stream = nullptr;       // stream of the synchronous entry points
-    hipEvent_t done = nullptr;          // end of the most recent call's work
-    bool done_valid = false;
-    hipEvent_t staging_free = nullptr;  // the last parameter upload has been consumed
-    bool staging_valid = false;
     // timing ring: slot i holds the events of one timed call (start, after
     // the distance kernel, end); a slot is folded into the totals before reuse
     static constexpr int kTimingSlots = 64;
@@ -77,13 +94,16 @@ struct wmd_corpus {
     double dist_ms_total = 0.0, sink_ms_total = 0.0;
     float last_dist_ms = 0.f, last_sink_ms = 0.f;
     int last_launches = 0;
-    wmd::Workspace ws;
+    wmd::Workspace ws[wmd::kWorkSlots];
+    int next_ws = 0;
+    wmd::Staging stage;
 };
 
 namespace wmd {
 int plan_query(const wmd_corpus* c, const int32_t* qids, const float* qw, int32_t n, float lambda,
                int32_t iters, int bf16, PlannedQuery* out);
+// Enqueue a call; *slot receives the workspace slot it used.
 int run_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_query_options& opt,
-                double* dev_out, double* dev_res, hipStream_t stream, bool need_host_out);
+                double* dev_out, double* dev_res, hipStream_t stream, bool need_host_out, int* slot);
 int fold_timing_slot(wmd_corpus* c, int slot);
 }  // namespace wmd

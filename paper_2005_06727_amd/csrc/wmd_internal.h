@@ -20,7 +20,8 @@ struct QueryDev {
     const float* r;        // m query weights r_k (sum 1)
     const float* rinv;     // m values 1 / r_k
     float* Kt;             // U x ldk: Kt[i, k] = K[k, word(i)] (optionally column-shifted)
-    float* KMt;            // U x ldk: Kt[i, k] * M[k, word(i)]
+    float* KMt;            // U x ldk: Kt[i, k] * M[k, word(i)] (written only when km_from_k == 0)
+    float* nrow;           // U: log-domain shift n_i = min_k M[k, word(i)] (shift != 0 only)
     float* x;              // N x ldk iterate x (documents in length-sorted order),
                            // used only when iterations span several launches
     double* out;           // N distances, input document order
@@ -31,6 +32,8 @@ struct QueryDev {
     int32_t ldk;           // row stride of Kt / KMt / x (multiple of 4, >= m)
     int32_t iters;         // x updates
     int32_t shift;         // log-domain column shift on/off
+    int32_t km_from_k;     // the final step rebuilds K .* M from K: M = n_i - ln(K) / lambda
+    float inv_lambda;      // 1 / lambda (km_from_k only)
 };
 
 // Device-resident corpus (all arrays on `device`).
@@ -74,14 +77,17 @@ hipError_t launch_prep_docs(const int32_t* ptr, const float* w, float* cw, int64
 hipError_t launch_gather_rows(const float* vecs, const int32_t* ids, float* out, int64_t nrows, int ldv,
                               hipStream_t s);
 
-// Distance GEMM + epilogue for queries qd[0..B): writes Kt / KMt.
-hipError_t launch_dist(const DevCorpus& c, const QueryDev* qd, int B, int max_m, int bf16,
+// Distance GEMM + epilogue: writes Kt / KMt of every query; the queries are
+// split into `groups` contiguous groups, qgroup[g] .. qgroup[g+1] (device).
+hipError_t launch_dist(const DevCorpus& c, const QueryDev* qd, const int32_t* qgroup, int groups, int bf16,
                        hipStream_t s);
 
 // Fused Sinkhorn iterations + final WMD step.  `shape` selects the register
 // tile (see k_sinkhorn.hip); shape < 0 selects the streaming kernel that
 // handles any size.
+int sinkhorn_num_shapes();
 int sinkhorn_shape_for(int m, int max_n);   // -1 when only the streaming kernel fits
+bool sinkhorn_shape_fits(int shape, int m, int max_n);
 int sinkhorn_shape_max_m(int shape);
 int sinkhorn_shape_max_n(int shape);
 hipError_t launch_sinkhorn(int shape, const SinkArgs& a, int max_m, int max_n, hipStream_t s);

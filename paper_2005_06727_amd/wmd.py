@@ -48,7 +48,7 @@ class wmd_corpus_options(C.Structure):
 
 class wmd_query_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("recompute_below", C.c_float),
-                ("log_domain", C.c_int32), ("iters_per_launch", C.c_int32)]
+                ("log_domain", C.c_int32), ("iters_per_launch", C.c_int32), ("tile", C.c_int32)]
 
 
 class wmd_corpus_info(C.Structure):
@@ -120,13 +120,15 @@ def _ptr(a: np.ndarray, ctype):
     return a.ctypes.data_as(C.POINTER(ctype))
 
 
-def _qopts(precision=WMD_DIST_FP32, recompute_below=-1.0, log_domain=False, iters_per_launch=0):
+def _qopts(precision=WMD_DIST_FP32, recompute_below=-1.0, log_domain=False, iters_per_launch=0,
+           tile=-1):
     o = wmd_query_options()
     _lib.wmd_query_options_init(C.byref(o))
     o.precision = int(precision)
     o.recompute_below = float(recompute_below)
     o.log_domain = int(bool(log_domain))
     o.iters_per_launch = int(iters_per_launch)
+    o.tile = int(tile)
     return o
 
 

@@ -267,3 +267,30 @@ def test_c2_paper_shape_sampled(wmd):
     print(f"c2 (V=100k, N=5000, v_r={q.size}): max rel err {e.max():.2e} on {docs.size} sampled docs")
     assert e.max() <= FP32_RTOL
     assert np.all(np.isfinite(got)) and np.all(got > 0)
+
+
+TILE_MAX_M = {0: 16, 1: 32, 2: 32, 3: 64, 4: 64, 5: 128, 6: 256, 7: 512, 8: 16, 9: 32, 10: 64}
+
+
+@pytest.mark.parametrize("tile", [-2] + sorted(TILE_MAX_M))
+def test_every_tile_shape(ragged, wmd, tile):
+    (vecs, ptr, ids, w), c = ragged
+    rng = np.random.default_rng(50 + tile)
+    top = TILE_MAX_M.get(tile, 600)
+    for m in sorted({1, 3, top // 2 + 1, top}):
+        q = rng.choice(vecs.shape[0], m, replace=False).astype(np.int32)
+        qw = rng.geometric(0.5, m).astype(np.float32)
+        got, res = c.query(q, qw, 10.0, 15, resid=True, tile=tile)
+        want, wres = sinkhorn_wmd_sparse(vecs, q, qw, ptr, ids, w, 10.0, 15)
+        e = rel_err(got, want)
+        print(f"tile={tile} m={m}: max rel err {e.max():.2e}")
+        assert e.max() <= FP32_RTOL
+        np.testing.assert_allclose(res, wres, rtol=2e-2, atol=1e-6)
+        again, _ = c.query(q, qw, 10.0, 15, tile=tile, iters_per_launch=4)
+        assert np.array_equal(got, again)
+    if tile >= 0:
+        m = top + 1
+        q = rng.choice(vecs.shape[0], m, replace=False).astype(np.int32)
+        with pytest.raises(wmd.WmdError) as ex:
+            c.query(q, np.ones(m, np.float32), 10.0, 15, tile=tile)
+        assert ex.value.code == wmd.WMD_EINVAL
