@@ -207,11 +207,81 @@ typedef struct wmd_timing {
     double sinkhorn_ms;       /* Sinkhorn iterations + final WMD step, summed */
     float last_dist_ms;       /* the most recent timed call */
     float last_sinkhorn_ms;
-    int32_t launches;         /* kernel launches of the most recent call */
+    int32_t launches;         /* kernel launches of the most recent timed call */
 } wmd_timing;
 
 int wmd_set_timing(wmd_corpus* corpus, int32_t enable);
 int wmd_timing_get(wmd_corpus* corpus, wmd_timing* out);
+
+/*
+ * Serving: continuous batching of queries against a device-resident corpus
+ * (the paper's one-query-against-many evaluation, Sec. 3, applied to a stream
+ * of queries).
+ *
+ * A server owns a worker thread, `max_inflight` HIP streams and one device
+ * workspace per stream, carved from `hbm_budget_bytes` (each stream gets an
+ * equal share, allocated at creation).  Submitted queries wait in FIFO order;
+ * whenever a stream is free the worker launches the longest FIFO prefix (at
+ * most `max_batch` queries) whose workspace fits that stream's share, so
+ * batches admitted while others run overlap on the device.  Every query's
+ * result is bitwise the one wmd_query returns for it with the same options:
+ * a document's computation does not depend on the rest of the batch.
+ */
+typedef struct wmd_server wmd_server;
+
+typedef struct wmd_server_options {
+    int64_t hbm_budget_bytes;  /* device memory of all stream workspaces together (> 0) */
+    int32_t max_batch;         /* queries per device batch (>= 1) */
+    int32_t max_inflight;      /* concurrent batches, one stream each (1..16) */
+    int32_t want_resid;        /* also keep the FP64 row-marginal residuals */
+    int32_t batch_wait_us;     /* how long a lone waiting query may wait for others to
+                                  batch with (0: launch at once) */
+    wmd_query_options query;   /* options of every query */
+} wmd_server_options;
+
+typedef struct wmd_server_stats {
+    int64_t submitted, completed, batches;
+    double latency_p50_ms;     /* submit -> result ready, over completed queries */
+    double latency_p99_ms;
+    double latency_mean_ms;
+    double latency_max_ms;
+    double queries_per_s;      /* completed / (last completion - first submission) */
+    double doc_iters_per_s;    /* sum over completed queries of N * iters, per second */
+    double mean_batch;         /* queries per launched batch */
+    int64_t workspace_bytes;   /* device memory held by the server */
+} wmd_server_stats;
+
+/* Defaults: 4 GiB budget, batches of 16, 2 streams, no residuals, no batching
+ * wait, default query options. */
+void wmd_server_options_init(wmd_server_options* opt);
+
+/* Create a server on `corpus` (which must outlive it).  Errors: WMD_EINVAL for
+ * bad options (budget <= 0, max_batch < 1, max_inflight outside 1..16,
+ * invalid query options, BF16 without BF16 corpus copies), WMD_ENOMEM,
+ * WMD_EDEVICE. */
+int wmd_server_create(wmd_corpus* corpus, const wmd_server_options* opt, wmd_server** out);
+
+/* Queue one query (arguments as wmd_query; host arrays copied before return).
+ * Returns a ticket >= 0, or WMD_EINVAL for an invalid query, WMD_ENOMEM when
+ * the query alone does not fit one stream's share of the budget,
+ * WMD_ESHUTDOWN while the server is being destroyed. */
+int64_t wmd_server_submit(wmd_server* server, const int32_t* qids, const float* qweights, int32_t n,
+                          float lambda, int32_t iters);
+
+/* Wait up to timeout_us (< 0: forever) for a ticket; on success write N
+ * distances (and N residuals when requested at creation and out_resid is
+ * non-null) and forget the ticket.  WMD_ETIMEDOUT keeps the ticket;
+ * WMD_ENOTFOUND for an unknown or collected ticket; a device error of the
+ * ticket's batch is returned as WMD_EDEVICE. */
+int wmd_server_wait(wmd_server* server, int64_t ticket, double* out_dist, double* out_resid,
+                    int64_t timeout_us);
+
+/* Counters and latency percentiles since creation. */
+int wmd_server_stats_get(wmd_server* server, wmd_server_stats* out);
+
+/* Finish every queued and running query, then release the server.  Results
+ * not collected by then are dropped.  NULL is a no-op. */
+void wmd_server_destroy(wmd_server* server);
 
 /* Message describing the last non-zero status returned to this thread. */
 const char* wmd_last_error(void);

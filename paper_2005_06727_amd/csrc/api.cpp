@@ -64,6 +64,48 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 }  // namespace
 
+void free_workspace(Workspace& w) {
+    if (!w.carved) {
+        dfree(w.Kt);
+        dfree(w.KMt);
+        dfree(w.x);
+        dfree(w.nrow);
+        dfree(w.params);
+        dfree(w.out);
+    }
+    w.Kt = w.KMt = w.x = w.nrow = nullptr;
+    w.params = nullptr;
+    w.out = nullptr;
+    hfree(w.h_out);
+    w.kcap = w.kmcap = w.xcap = w.ncap = w.pcap = w.ocap = w.hocap = 0;
+    w.carved = false;
+    if (w.done) (void)hipEventDestroy(w.done);
+    w.done = nullptr;
+    w.done_valid = false;
+}
+
+void free_staging(Staging& st) {
+    for (int i = 0; i < Staging::kSlots; ++i) {
+        hfree(st.h[i]);
+        if (st.ev[i]) (void)hipEventDestroy(st.ev[i]);
+        st.ev[i] = nullptr;
+        st.pending[i] = false;
+    }
+    st.cap = 0;
+}
+
+int check_query_options(const wmd_query_options* in, wmd_query_options* o) {
+    wmd_query_options_init(o);
+    if (in) *o = *in;
+    if (o->precision != WMD_DIST_FP32 && o->precision != WMD_DIST_BF16)
+        return fail(WMD_EINVAL, "options: unknown precision %d", o->precision);
+    if (!std::isfinite(o->recompute_below)) return fail(WMD_EINVAL, "options: recompute_below not finite");
+    if (o->iters_per_launch < 0) return fail(WMD_EINVAL, "options: iters_per_launch < 0");
+    if (o->tile < -2 || o->tile >= sinkhorn_num_shapes())
+        return fail(WMD_EINVAL, "options: tile %d outside [-2, %d)", o->tile, sinkhorn_num_shapes());
+    return WMD_OK;
+}
+
 // ---------------------------------------------------------------- queries
 
 int plan_query(const wmd_corpus* c, const int32_t* qids, const float* qw, int32_t n, float lambda,
@@ -106,10 +148,77 @@ int plan_query(const wmd_corpus* c, const int32_t* qids, const float* qw, int32_
     return WMD_OK;
 }
 
-static int ensure_workspace(Workspace& w, size_t kfloats, size_t xfloats, size_t nfloats, size_t pbytes,
-                            size_t obytes, bool need_host_out) {
-    const bool grow = kfloats > w.kcap || xfloats > w.xcap || nfloats > w.ncap || pbytes > w.pcap ||
-                      obytes > w.ocap || (need_host_out && obytes > w.hocap);
+Layout make_layout(const wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_query_options& opt,
+                   bool resid, bool host_out) {
+    Layout L;
+    const int B = (int)qs.size();
+    const int64_t N = c->dc.N, U = c->dc.U;
+    bool any_km = false;
+    for (const auto& q : qs) {
+        L.sum_ldk += q.ldk;
+        L.sum_m += q.m;
+        L.max_iters = std::max(L.max_iters, q.iters);
+        L.max_m = std::max(L.max_m, q.m);
+        any_km = any_km || q.lambda < kKmFromKMinLambda;
+    }
+    L.per_launch = opt.iters_per_launch > 0 ? opt.iters_per_launch : INT_MAX;
+    L.chunked = L.per_launch < L.max_iters;
+    L.kfloats = (size_t)U * L.sum_ldk;
+    L.kmfloats = any_km ? L.kfloats : 0;
+    L.xfloats = L.chunked ? (size_t)N * L.sum_ldk : 0;
+    L.nfloats = opt.log_domain ? (size_t)U * B : 0;
+    // distance-kernel groups: contiguous runs of queries with balanced column counts,
+    // enough of them that row tiles x groups fills the device
+    const int64_t tile_rows = opt.precision == WMD_DIST_BF16 ? 64 : 32;
+    const int64_t row_tiles = (U + tile_rows - 1) / tile_rows;
+    L.G = (int)std::max<int64_t>(1, std::min<int64_t>(B, (4096 + row_tiles - 1) / row_tiles));
+    // parameter block: QueryDev[B] | qlist[B] | qgroup[G+1] | qid[sum_m] | r[sum_m] | rinv[sum_m]
+    L.off_ql = align_up(sizeof(QueryDev) * B, 256);
+    L.off_qg = align_up(L.off_ql + sizeof(int32_t) * B, 256);
+    L.off_id = align_up(L.off_qg + sizeof(int32_t) * (L.G + 1), 256);
+    L.off_r = align_up(L.off_id + sizeof(int32_t) * L.sum_m, 256);
+    L.off_ri = align_up(L.off_r + sizeof(float) * L.sum_m, 256);
+    L.pbytes = align_up(L.off_ri + sizeof(float) * L.sum_m, 256);
+    L.obytes = host_out ? sizeof(double) * (size_t)B * N * (resid ? 2 : 1) : 0;
+    return L;
+}
+
+size_t Layout::device_bytes() const {
+    return align_up(sizeof(float) * kfloats, 256) + align_up(sizeof(float) * kmfloats, 256) +
+           align_up(sizeof(float) * xfloats, 256) + align_up(sizeof(float) * nfloats, 256) + pbytes +
+           align_up(obytes, 256);
+}
+
+// Point w's buffers into one device allocation of at least L.device_bytes().
+void carve_workspace(Workspace& w, char* base, const Layout& L) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base + off;
+        off += align_up(bytes, 256);
+        return p;
+    };
+    w.Kt = reinterpret_cast<float*>(take(sizeof(float) * L.kfloats));
+    w.KMt = reinterpret_cast<float*>(take(sizeof(float) * L.kmfloats));
+    w.x = reinterpret_cast<float*>(take(sizeof(float) * L.xfloats));
+    w.nrow = reinterpret_cast<float*>(take(sizeof(float) * L.nfloats));
+    w.params = take(L.pbytes);
+    w.out = reinterpret_cast<double*>(take(L.obytes));
+    w.kcap = L.kfloats;
+    w.kmcap = L.kmfloats;
+    w.xcap = L.xfloats;
+    w.ncap = L.nfloats;
+    w.pcap = L.pbytes;
+    w.ocap = L.obytes;
+    w.carved = true;
+}
+
+static int ensure_workspace(Workspace& w, const Layout& L, bool need_host_out) {
+    const size_t kfloats = L.kfloats, kmfloats = L.kmfloats, xfloats = L.xfloats, nfloats = L.nfloats;
+    const size_t pbytes = L.pbytes, obytes = L.obytes;
+    const bool grow_dev = kfloats > w.kcap || kmfloats > w.kmcap || xfloats > w.xcap || nfloats > w.ncap ||
+                          pbytes > w.pcap || obytes > w.ocap;
+    if (grow_dev && w.carved) return fail(WMD_ENOMEM, "workspace: batch exceeds its carved device memory");
+    const bool grow = grow_dev || (need_host_out && obytes > w.hocap);
     if (!grow) return WMD_OK;
     // nothing queued may still use this slot's old buffers
     if (w.done_valid) {
@@ -120,12 +229,17 @@ static int ensure_workspace(Workspace& w, size_t kfloats, size_t xfloats, size_t
     auto grown = [](size_t need) { return need + need / 4; };
     if (kfloats > w.kcap) {
         dfree(w.Kt);
-        dfree(w.KMt);
         w.kcap = 0;
         size_t cap = grown(kfloats);
-        if ((e = dalloc(&w.Kt, cap)) != hipSuccess || (e = dalloc(&w.KMt, cap)) != hipSuccess)
-            return hip_fail(e, "workspace: K buffers");
+        if ((e = dalloc(&w.Kt, cap)) != hipSuccess) return hip_fail(e, "workspace: K buffer");
         w.kcap = cap;
+    }
+    if (kmfloats > w.kmcap) {
+        dfree(w.KMt);
+        w.kmcap = 0;
+        size_t cap = grown(kmfloats);
+        if ((e = dalloc(&w.KMt, cap)) != hipSuccess) return hip_fail(e, "workspace: K.*M buffer");
+        w.kmcap = cap;
     }
     if (xfloats > w.xcap) {
         dfree(w.x);
@@ -168,8 +282,7 @@ static int ensure_workspace(Workspace& w, size_t kfloats, size_t xfloats, size_t
 }
 
 // A pinned staging slot of at least `bytes`, free for writing.
-static int take_staging(wmd_corpus* c, size_t bytes, int* slot_out) {
-    Staging& st = c->stage;
+static int take_staging(Staging& st, size_t bytes, int* slot_out) {
     hipError_t e;
     if (bytes > st.cap) {
         for (int i = 0; i < Staging::kSlots; ++i) {
@@ -218,41 +331,34 @@ int fold_timing_slot(wmd_corpus* c, int slot) {
 // dev_out (and dev_res when non-null) receives query b's N results.
 int run_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_query_options& opt,
                 double* dev_out, double* dev_res, hipStream_t stream, bool need_host_out, int* slot_used) {
+    const int wslot = c->next_ws;
+    c->next_ws = (c->next_ws + 1) % kWorkSlots;
+    *slot_used = wslot;
+    return enqueue_queries(c, qs, opt, dev_out, dev_res, stream, need_host_out, c->ws[wslot], c->stage,
+                           c->timing);
+}
+
+size_t workspace_bytes(const wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_query_options& opt,
+                       bool resid) {
+    return make_layout(c, qs, opt, resid, true).device_bytes();
+}
+
+int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_query_options& opt,
+                    double* dev_out, double* dev_res, hipStream_t stream, bool need_host_out, Workspace& w,
+                    Staging& st, bool timed) {
     const DevCorpus& dc = c->dc;
     const int B = (int)qs.size();
     const int64_t N = dc.N, U = dc.U;
-    size_t sum_ldk = 0, sum_m = 0;
-    int max_iters = 0, max_m = 0;
-    for (const auto& q : qs) {
-        sum_ldk += q.ldk;
-        sum_m += q.m;
-        max_iters = std::max(max_iters, q.iters);
-        max_m = std::max(max_m, q.m);
-    }
+    const Layout L = make_layout(c, qs, opt, dev_res != nullptr, need_host_out);
+    const int max_m = L.max_m, max_iters = L.max_iters, per_launch = L.per_launch, G = L.G;
+    const bool chunked = L.chunked;
+    const size_t sum_ldk = L.sum_ldk;
+    const size_t off_ql = L.off_ql, off_qg = L.off_qg, off_id = L.off_id, off_r = L.off_r, off_ri = L.off_ri;
+    const size_t pbytes = L.pbytes;
+    (void)max_iters;
     if (opt.tile >= 0 && !sinkhorn_shape_fits(opt.tile, max_m, 1))
         return fail(WMD_EINVAL, "options: tile %d cannot hold a %d-word query", opt.tile, max_m);
-    const int per_launch = opt.iters_per_launch > 0 ? opt.iters_per_launch : INT_MAX;
-    const bool chunked = per_launch < max_iters;
-    const size_t kfloats = (size_t)U * sum_ldk;
-    const size_t xfloats = chunked ? (size_t)N * sum_ldk : 0;
-    // distance-kernel groups: contiguous runs of queries with balanced column counts,
-    // enough of them that row tiles x groups fills the device
-    const int64_t row_tiles = (U + 63) / 64;
-    const int G = (int)std::max<int64_t>(1, std::min<int64_t>(B, (2048 + row_tiles - 1) / row_tiles));
-    // parameter block: QueryDev[B] | qlist[B] | qgroup[G+1] | qid[sum_m] | r[sum_m] | rinv[sum_m]
-    const size_t off_ql = align_up(sizeof(QueryDev) * B, 256);
-    const size_t off_qg = align_up(off_ql + sizeof(int32_t) * B, 256);
-    const size_t off_id = align_up(off_qg + sizeof(int32_t) * (G + 1), 256);
-    const size_t off_r = align_up(off_id + sizeof(int32_t) * sum_m, 256);
-    const size_t off_ri = align_up(off_r + sizeof(float) * sum_m, 256);
-    const size_t pbytes = align_up(off_ri + sizeof(float) * sum_m, 256);
-    const size_t obytes = need_host_out ? sizeof(double) * (size_t)B * N * (dev_res ? 2 : 1) : 0;
-    const size_t nfloats = opt.log_domain ? (size_t)U * B : 0;
-    const int wslot = c->next_ws;
-    c->next_ws = (c->next_ws + 1) % kWorkSlots;
-    Workspace& w = c->ws[wslot];
-    *slot_used = wslot;
-    int rc = ensure_workspace(w, kfloats, xfloats, nfloats, pbytes, obytes, need_host_out);
+    int rc = ensure_workspace(w, L, need_host_out);
     if (rc) return rc;
     if (need_host_out) {
         dev_out = w.out;
@@ -260,8 +366,8 @@ int run_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_qu
     }
 
     int slot_s = 0;
-    if ((rc = take_staging(c, pbytes, &slot_s))) return rc;
-    char* hp = c->stage.h[slot_s];
+    if ((rc = take_staging(st, pbytes, &slot_s))) return rc;
+    char* hp = st.h[slot_s];
     char* dp = w.params;
     QueryDev* hq = reinterpret_cast<QueryDev*>(hp);
     int32_t* hql = reinterpret_cast<int32_t*>(hp + off_ql);
@@ -279,7 +385,7 @@ int run_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_qu
         d.r = reinterpret_cast<const float*>(dp + off_r) + mo;
         d.rinv = reinterpret_cast<const float*>(dp + off_ri) + mo;
         d.Kt = w.Kt + (size_t)U * ko;
-        d.KMt = w.KMt + (size_t)U * ko;
+        d.KMt = L.kmfloats ? w.KMt + (size_t)U * ko : nullptr;
         d.x = chunked ? w.x + (size_t)N * ko : nullptr;
         d.out = dev_out + (size_t)b * N;
         d.resid = dev_res ? dev_res + (size_t)b * N : nullptr;
@@ -331,14 +437,14 @@ int run_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_qu
         return hip_fail(e, "query: order after the slot's previous call");
     if ((e = hipMemcpyAsync(dp, hp, pbytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
         return hip_fail(e, "query: upload parameters");
-    if ((e = hipEventRecord(c->stage.ev[slot_s], stream)) != hipSuccess) return hip_fail(e, "query: record");
-    c->stage.pending[slot_s] = true;
+    if ((e = hipEventRecord(st.ev[slot_s], stream)) != hipSuccess) return hip_fail(e, "query: record");
+    st.pending[slot_s] = true;
 
     const QueryDev* dq = reinterpret_cast<const QueryDev*>(dp);
     const int32_t* dql = reinterpret_cast<const int32_t*>(dp + off_ql);
     int launches = 0;
     int slot = -1;
-    if (c->timing) {
+    if (timed) {
         slot = c->next_slot;
         c->next_slot = (c->next_slot + 1) % wmd_corpus::kTimingSlots;
         if (c->slot_pending[slot] && (rc = fold_timing_slot(c, slot))) return rc;
@@ -385,8 +491,8 @@ int run_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_qu
         (void)hipEventRecord(c->ev[slot][2], stream);
         c->slot_pending[slot] = true;
         c->last_slot = slot;
+        c->last_launches = launches;
     }
-    c->last_launches = launches;
     if ((e = hipEventRecord(w.done, stream)) != hipSuccess) return hip_fail(e, "query: record");
     w.done_valid = true;
     return WMD_OK;
@@ -429,21 +535,8 @@ static void corpus_free(wmd_corpus* c) {
     dfree(d.scol);
     dfree(d.scw);
     dfree(d.sdoc);
-    for (int sl = 0; sl < kWorkSlots; ++sl) {
-        Workspace& w = c->ws[sl];
-        dfree(w.Kt);
-        dfree(w.KMt);
-        dfree(w.x);
-        dfree(w.nrow);
-        dfree(w.params);
-        dfree(w.out);
-        hfree(w.h_out);
-        if (w.done) (void)hipEventDestroy(w.done);
-    }
-    for (int i = 0; i < Staging::kSlots; ++i) {
-        hfree(c->stage.h[i]);
-        if (c->stage.ev[i]) (void)hipEventDestroy(c->stage.ev[i]);
-    }
+    for (int sl = 0; sl < kWorkSlots; ++sl) free_workspace(c->ws[sl]);
+    free_staging(c->stage);
     for (int i = 0; i < wmd_corpus::kTimingSlots; ++i)
         for (int j = 0; j < 3; ++j)
             if (c->ev[i][j]) (void)hipEventDestroy(c->ev[i][j]);
@@ -618,18 +711,6 @@ int wmd_corpus_info_get(const wmd_corpus* c, wmd_corpus_info* out) {
     return WMD_OK;
 }
 
-static int check_opts(const wmd_query_options* in, wmd_query_options* o) {
-    wmd_query_options_init(o);
-    if (in) *o = *in;
-    if (o->precision != WMD_DIST_FP32 && o->precision != WMD_DIST_BF16)
-        return fail(WMD_EINVAL, "options: unknown precision %d", o->precision);
-    if (!std::isfinite(o->recompute_below)) return fail(WMD_EINVAL, "options: recompute_below not finite");
-    if (o->iters_per_launch < 0) return fail(WMD_EINVAL, "options: iters_per_launch < 0");
-    if (o->tile < -2 || o->tile >= sinkhorn_num_shapes())
-        return fail(WMD_EINVAL, "options: tile %d outside [-2, %d)", o->tile, sinkhorn_num_shapes());
-    return WMD_OK;
-}
-
 static int batch_plan(wmd_corpus* c, int32_t B, const int64_t* q_ptr, const int32_t* qids, const float* qw,
                       const float* lambdas, const int32_t* iters, const wmd_query_options& o,
                       std::vector<PlannedQuery>* qs) {
@@ -667,7 +748,7 @@ int wmd_query(wmd_corpus* c, const int32_t* qids, const float* qweights, int32_t
               const wmd_query_options* opt, double* out_dist, double* out_resid) {
     if (!c || !out_dist) return fail(WMD_EINVAL, "query: null corpus or output");
     wmd_query_options o;
-    int rc = check_opts(opt, &o);
+    int rc = wmd::check_query_options(opt, &o);
     if (rc) return rc;
     std::vector<PlannedQuery> qs(1);
     if ((rc = plan_query(c, qids, qweights, n, lambda, iters, o.precision == WMD_DIST_BF16, &qs[0]))) return rc;
@@ -685,7 +766,7 @@ int wmd_query_async(wmd_corpus* c, const int32_t* qids, const float* qweights, i
                     void* stream) {
     if (!c || !dev_dist) return fail(WMD_EINVAL, "query: null corpus or output");
     wmd_query_options o;
-    int rc = check_opts(opt, &o);
+    int rc = wmd::check_query_options(opt, &o);
     if (rc) return rc;
     std::vector<PlannedQuery> qs(1);
     if ((rc = plan_query(c, qids, qweights, n, lambda, iters, o.precision == WMD_DIST_BF16, &qs[0]))) return rc;
@@ -701,7 +782,7 @@ int wmd_query_batch(wmd_corpus* c, int32_t B, const int64_t* q_ptr, const int32_
                     double* out_resid) {
     if (!c || !out_dist) return fail(WMD_EINVAL, "batch: null corpus or output");
     wmd_query_options o;
-    int rc = check_opts(opt, &o);
+    int rc = wmd::check_query_options(opt, &o);
     if (rc) return rc;
     std::vector<PlannedQuery> qs;
     if ((rc = batch_plan(c, B, q_ptr, qids, qweights, lambdas, iters, o, &qs))) return rc;
@@ -719,7 +800,7 @@ int wmd_query_batch_async(wmd_corpus* c, int32_t B, const int64_t* q_ptr, const 
                           const wmd_query_options* opt, double* dev_dist, double* dev_resid, void* stream) {
     if (!c || !dev_dist) return fail(WMD_EINVAL, "batch: null corpus or output");
     wmd_query_options o;
-    int rc = check_opts(opt, &o);
+    int rc = wmd::check_query_options(opt, &o);
     if (rc) return rc;
     std::vector<PlannedQuery> qs;
     if ((rc = batch_plan(c, B, q_ptr, qids, qweights, lambdas, iters, o, &qs))) return rc;

@@ -639,7 +639,7 @@ const Shape kShapes[] = {
 };
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 // default shape per query-length class (first entry whose max_m covers m)
-const int kDefaultShapes[] = {0, 2, 4, 5, 6, 7};
+const int kDefaultShapes[] = {8, 2, 4, 5, 6, 7};   // chosen by measurement on the c2-shaped corpus
 
 }  // namespace
 

@@ -24,7 +24,8 @@ constexpr float kKmFromKMinLambda = 0.5f;  // from this lambda on, K .* M is reb
 struct Workspace {
     float* Kt = nullptr;
     float* KMt = nullptr;
-    size_t kcap = 0;          // floats in each of Kt, KMt
+    size_t kcap = 0;          // floats in Kt
+    size_t kmcap = 0;         // floats in KMt (only queries with small lambda read it)
     float* x = nullptr;
     size_t xcap = 0;
     float* nrow = nullptr;    // per-query log-domain row shifts (U each)
@@ -37,8 +38,19 @@ struct Workspace {
     size_t hocap = 0;
     hipEvent_t done = nullptr;
     bool done_valid = false;
+    bool carved = false;      // buffers point into memory owned elsewhere (fixed capacity)
 };
 constexpr int kWorkSlots = 2;
+
+// Sizes and offsets of one call's workspace and parameter block.
+struct Layout {
+    size_t kfloats = 0, kmfloats = 0, xfloats = 0, nfloats = 0, pbytes = 0, obytes = 0;
+    size_t sum_ldk = 0, sum_m = 0;
+    size_t off_ql = 0, off_qg = 0, off_id = 0, off_r = 0, off_ri = 0;
+    int G = 1, max_m = 0, max_iters = 0, per_launch = 0;
+    bool chunked = false;
+    size_t device_bytes() const;
+};
 
 // Pinned host staging of the parameter blocks: a ring, so the host can enqueue
 // several calls ahead of the device; slot i is reusable once its upload
@@ -100,10 +112,23 @@ struct wmd_corpus {
 };
 
 namespace wmd {
+Layout make_layout(const wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_query_options& opt,
+                   bool resid, bool host_out);
 int plan_query(const wmd_corpus* c, const int32_t* qids, const float* qw, int32_t n, float lambda,
                int32_t iters, int bf16, PlannedQuery* out);
-// Enqueue a call; *slot receives the workspace slot it used.
+// Enqueue a call on the corpus's own workspace slots; *slot receives the slot used.
 int run_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_query_options& opt,
                 double* dev_out, double* dev_res, hipStream_t stream, bool need_host_out, int* slot);
 int fold_timing_slot(wmd_corpus* c, int slot);
+// Enqueue a call on an explicit workspace and staging ring (the server's own).
+int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_query_options& opt,
+                    double* dev_out, double* dev_res, hipStream_t stream, bool need_host_out, Workspace& w,
+                    Staging& st, bool timed);
+// Device bytes a call's workspace needs (K buffers, row shifts, iterate, results).
+size_t workspace_bytes(const wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_query_options& opt,
+                       bool resid);
+void free_workspace(Workspace& w);
+void carve_workspace(Workspace& w, char* base, const Layout& L);
+void free_staging(Staging& st);
+int check_query_options(const wmd_query_options* in, wmd_query_options* out);
 }  // namespace wmd

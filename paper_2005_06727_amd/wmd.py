@@ -62,6 +62,19 @@ class wmd_timing(C.Structure):
                 ("last_dist_ms", C.c_float), ("last_sinkhorn_ms", C.c_float), ("launches", C.c_int32)]
 
 
+class wmd_server_options(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_batch", C.c_int32), ("max_inflight", C.c_int32),
+                ("want_resid", C.c_int32), ("batch_wait_us", C.c_int32), ("query", wmd_query_options)]
+
+
+class wmd_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("batches", C.c_int64),
+                ("latency_p50_ms", C.c_double), ("latency_p99_ms", C.c_double),
+                ("latency_mean_ms", C.c_double), ("latency_max_ms", C.c_double),
+                ("queries_per_s", C.c_double), ("doc_iters_per_s", C.c_double),
+                ("mean_batch", C.c_double), ("workspace_bytes", C.c_int64)]
+
+
 _P = C.c_void_p
 _i32p, _i64p = C.POINTER(C.c_int32), C.POINTER(C.c_int64)
 _f32p, _f64p = C.POINTER(C.c_float), C.POINTER(C.c_double)
@@ -90,6 +103,12 @@ _sig("wmd_query_batch_async", C.c_int, _P, C.c_int32, _i64p, _i32p, _f32p, _f32p
      C.POINTER(wmd_query_options), _P, _P, _P)
 _sig("wmd_set_timing", C.c_int, _P, C.c_int32)
 _sig("wmd_timing_get", C.c_int, _P, C.POINTER(wmd_timing))
+_sig("wmd_server_options_init", None, C.POINTER(wmd_server_options))
+_sig("wmd_server_create", C.c_int, _P, C.POINTER(wmd_server_options), C.POINTER(_P))
+_sig("wmd_server_submit", C.c_int64, _P, _i32p, _f32p, C.c_int32, C.c_float, C.c_int32)
+_sig("wmd_server_wait", C.c_int, _P, C.c_int64, _f64p, _f64p, C.c_int64)
+_sig("wmd_server_stats_get", C.c_int, _P, C.POINTER(wmd_server_stats))
+_sig("wmd_server_destroy", None, _P)
 
 
 def declared_functions() -> list:
@@ -255,6 +274,58 @@ def wmd_timing_get(corpus: int) -> dict:
     return {f: getattr(t, f) for f, _ in t._fields_}
 
 
+def wmd_server_options_init() -> wmd_server_options:
+    o = wmd_server_options()
+    _lib.wmd_server_options_init(C.byref(o))
+    return o
+
+
+def wmd_server_create(corpus: int, hbm_budget_bytes: Optional[int] = None, max_batch: Optional[int] = None,
+                      max_inflight: Optional[int] = None, want_resid: bool = False,
+                      batch_wait_us: int = 0, **opts) -> int:
+    o = wmd_server_options_init()
+    if hbm_budget_bytes is not None:
+        o.hbm_budget_bytes = int(hbm_budget_bytes)
+    if max_batch is not None:
+        o.max_batch = int(max_batch)
+    if max_inflight is not None:
+        o.max_inflight = int(max_inflight)
+    o.want_resid = int(bool(want_resid))
+    o.batch_wait_us = int(batch_wait_us)
+    o.query = _qopts(**opts)
+    h = _P()
+    _check(_lib.wmd_server_create(corpus, C.byref(o), C.byref(h)))
+    return h.value
+
+
+def wmd_server_submit(server: int, qids, qweights, lam: float, iters: int) -> int:
+    q, w = _arr(qids, np.int32), _arr(qweights, np.float32)
+    if q.shape != w.shape or q.ndim != 1:
+        raise ValueError("query ids and weights must be 1-D of equal length")
+    t = _lib.wmd_server_submit(server, _ptr(q, C.c_int32), _ptr(w, C.c_float), q.size, float(lam), int(iters))
+    if t < 0:
+        raise WmdError(int(t), wmd_last_error())
+    return int(t)
+
+
+def wmd_server_wait(server: int, ticket: int, N: int, resid: bool = False, timeout_us: int = -1):
+    out = np.empty(N, np.float64)
+    res = np.empty(N, np.float64) if resid else None
+    _check(_lib.wmd_server_wait(server, int(ticket), _ptr(out, C.c_double),
+                                _ptr(res, C.c_double) if resid else None, int(timeout_us)))
+    return out, res
+
+
+def wmd_server_stats_get(server: int) -> dict:
+    st = wmd_server_stats()
+    _check(_lib.wmd_server_stats_get(server, C.byref(st)))
+    return {f: getattr(st, f) for f, _ in st._fields_}
+
+
+def wmd_server_destroy(server: int) -> None:
+    _lib.wmd_server_destroy(server)
+
+
 class Corpus:
     """Owning handle: ``Corpus(vecs, doc_ptr, word_ids, weights).query(ids, w, lam, iters)``."""
 
@@ -271,6 +342,42 @@ class Corpus:
     def close(self):
         if getattr(self, "handle", None):
             wmd_corpus_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Owning handle of a continuous-batching server on a Corpus."""
+
+    def __init__(self, corpus: Corpus, **kw):
+        self.corpus = corpus
+        self.N = corpus.info["N"]
+        self.resid = bool(kw.get("want_resid", False))
+        self.handle = wmd_server_create(corpus.handle, **kw)
+
+    def submit(self, qids, qweights, lam, iters) -> int:
+        return wmd_server_submit(self.handle, qids, qweights, lam, iters)
+
+    def wait(self, ticket, timeout_us=-1):
+        return wmd_server_wait(self.handle, ticket, self.N, self.resid, timeout_us)
+
+    def stats(self) -> dict:
+        return wmd_server_stats_get(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            wmd_server_destroy(self.handle)
             self.handle = None
 
     def __enter__(self):

@@ -69,3 +69,17 @@ def test_product_path_does_not_import_oracle():
                 if isinstance(node, (ast.Import, ast.ImportFrom)):
                     mods = [a.name for a in node.names] if isinstance(node, ast.Import) else [node.module or ""]
                     assert not any(m.split(".")[0] == "oracle" for m in mods), f
+
+
+def test_server_option_defaults_and_null_corpus():
+    o = wmd.wmd_server_options_init()
+    assert (o.hbm_budget_bytes, o.max_batch, o.max_inflight, o.want_resid, o.batch_wait_us) == (
+        4 << 30, 16, 2, 0, 0)
+    assert (o.query.precision, o.query.tile) == (0, -1)
+    with pytest.raises(wmd.WmdError) as e:
+        wmd.wmd_server_create(None)
+    assert e.value.code == wmd.WMD_EINVAL
+    with pytest.raises(wmd.WmdError) as e:
+        wmd.wmd_server_submit(None, [1], [1.0], 1.0, 1)
+    assert e.value.code == wmd.WMD_EINVAL
+    wmd.wmd_server_destroy(None)
