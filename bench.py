@@ -1,6 +1,7 @@
 """Throughput of the sparse Sinkhorn WMD hot path on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+    python bench.py --serve c5 [--queries Q] [--qps R]
 
 One step = one query through the whole path (query preparation, distance GEMM
 + K epilogue, 15 fused Sinkhorn iterations + final WMD step) against the
@@ -8,9 +9,16 @@ device-resident corpus, results written to device memory.  Workload: the
 paper-shaped single query (V=100000 words, 300-dim embeddings, N=5000
 documents of 10-60 distinct Zipf(1.1) words, one query of 20-40 words,
 lambda=10, 15 iterations), seeded synthetic data standing in for the paper's
-crawl embeddings and DBpedia documents.
+crawl embeddings and DBpedia documents.  Consecutive queries alternate
+between two streams, so one query's distance GEMM overlaps the previous
+query's Sinkhorn kernel.
 
-Prints one JSON line: value = documents x iterations / second for the query.
+Prints one JSON line: value = documents x iterations / second.  The line also
+carries the 64-query batch on the same corpus (v_r 5-200) served three ways
+(back-to-back plain calls, one batch call, the continuous-batching server),
+with p50/p99 latency under Poisson arrivals.  ``--serve c5`` instead runs the
+served stream on the 100000-document corpus (BF16 distances) against plain
+FP32 calls and prints its own JSON line.
 """
 from __future__ import annotations
 
@@ -40,6 +48,14 @@ def parse():
     p.add_argument("--latency-calls", type=int, default=300)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--no-batch", action="store_true", help="skip the 64-query batch section")
+    p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                   help="also run one device copy of this many MiB (reference for HBM counters)")
+    p.add_argument("--serve", default=None, choices=["c5"], help="run the served-stream benchmark")
+    p.add_argument("--queries", type=int, default=2000)
+    p.add_argument("--qps", type=float, default=0.0, help="offered rate (0: 80%% of plain capacity)")
+    p.add_argument("--max-batch", type=int, default=16)
+    p.add_argument("--hbm-budget-gib", type=float, default=16.0)
     return p.parse_args()
 
 
@@ -84,6 +100,166 @@ def cpu_baseline(wl, q, qw, budget_s: float) -> dict:
                       f"single-threaded numpy; host has {os.cpu_count()} CPUs"}
 
 
+def open_loop_plain(corpus, queries, arrivals_s, lam, iters, **opts):
+    """FIFO single-caller service of Poisson arrivals with synchronous wmd_query:
+    latency = completion - arrival."""
+    lat = []
+    t0 = time.perf_counter()
+    for (q, qw), a in zip(queries, arrivals_s):
+        while time.perf_counter() - t0 < a:
+            pass
+        corpus.query(q, qw, lam, iters, **opts)
+        lat.append((time.perf_counter() - t0 - a) * 1e3)
+    span = time.perf_counter() - t0
+    return np.array(lat), span
+
+
+def open_loop_served(server, queries, arrivals_s, lam, iters):
+    """Submit at the arrival times from one thread, collect from another; the
+    server measures submit -> result latency itself."""
+    import threading
+    tickets = [None] * len(queries)
+    ready = threading.Semaphore(0)
+
+    def submitter():
+        t0 = time.perf_counter()
+        for i, ((q, qw), a) in enumerate(zip(queries, arrivals_s)):
+            while time.perf_counter() - t0 < a:
+                time.sleep(0)
+            tickets[i] = server.submit(q, qw, lam, iters)
+            ready.release()
+
+    t0 = time.perf_counter()
+    th = threading.Thread(target=submitter)
+    th.start()
+    for i in range(len(queries)):
+        ready.acquire()
+        server.wait(tickets[i])
+    th.join()
+    return time.perf_counter() - t0
+
+
+def pct(lat):
+    return {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+            "mean": float(np.mean(lat)), "max": float(np.max(lat))}
+
+
+def batch_section(wmd, corpus, sp, reps: int = 3) -> dict:
+    """The 64-query batch (v_r 5-200) on the single-query corpus: back-to-back
+    plain calls vs one batch call vs the server, plus open-loop latency."""
+    from paper_2005_06727_amd import synth
+    wl3 = synth.make("c3")
+    qs = [(np.ascontiguousarray(q, np.int32), np.ascontiguousarray(w, np.float32)) for q, w in wl3.queries]
+    lam, iters, N = wl3.spec.lam, wl3.spec.iters, corpus.info["N"]
+    B = len(qs)
+    work = B * N * iters
+
+    def best(f):
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            f()
+            ts.append(time.perf_counter() - t)
+        return min(ts)
+
+    ref = [corpus.query(q, w, lam, iters)[0] for q, w in qs]   # warm-up + reference
+    t_b2b = best(lambda: [corpus.query(q, w, lam, iters) for q, w in qs])
+    t_batch = best(lambda: corpus.query_batch(qs, lam, iters))
+    out = {"workload": f"{B} queries, v_r {min(len(q) for q, _ in qs)}-{max(len(q) for q, _ in qs)} "
+                       f"(uniform 5-200), same corpus, lambda={lam}, {iters} iterations, FP32",
+           "back_to_back": {"ms": t_b2b * 1e3, "doc_iters_per_s": work / t_b2b},
+           "batch_call": {"ms": t_batch * 1e3, "doc_iters_per_s": work / t_batch}}
+    with wmd.Server(corpus, max_batch=16, max_inflight=2) as srv:
+        def closed():
+            ts = [srv.submit(q, w, lam, iters) for q, w in qs]
+            return [srv.wait(t)[0] for t in ts]
+        got = closed()
+        assert all(np.array_equal(g, r) for g, r in zip(got, ref)), "served != plain"
+        t_srv = best(closed)
+        st = srv.stats()
+        out["served"] = {"ms": t_srv * 1e3, "doc_iters_per_s": work / t_srv, "mean_batch": st["mean_batch"],
+                         "max_batch": 16, "streams": 2,
+                         "vs_back_to_back": t_b2b / t_srv}
+    # open loop: Poisson arrivals at 70% of the back-to-back capacity, same sequence for both
+    rate = 0.7 * B / t_b2b
+    n_open = 4 * B
+    arr = np.cumsum(np.random.default_rng(7).exponential(1.0 / rate, size=n_open))
+    stream = [qs[i % B] for i in range(n_open)]
+    lat_plain, _ = open_loop_plain(corpus, stream, arr, lam, iters)
+    with wmd.Server(corpus, max_batch=16, max_inflight=2) as srv:
+        open_loop_served(srv, stream, arr, lam, iters)
+        st = srv.stats()
+    out["open_loop"] = {"qps": rate, "queries": n_open,
+                        "plain_latency_ms": pct(lat_plain),
+                        "served_latency_ms": {"p50": st["latency_p50_ms"], "p99": st["latency_p99_ms"],
+                                              "mean": st["latency_mean_ms"], "max": st["latency_max_ms"]},
+                        "served_mean_batch": st["mean_batch"]}
+    return out
+
+
+def serve_main(args):
+    """Served stream on the large corpus (BF16 distances, server) vs plain FP32
+    synchronous calls, same queries and Poisson arrival times."""
+    import torch
+    from paper_2005_06727_amd import synth, wmd
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    t = time.perf_counter()
+    wl = synth.make(args.serve, n_queries=args.queries)
+    sp = wl.spec
+    print(f"# {sp.name}: workload built in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+    corpus = wmd.Corpus(wl.vecs, wl.doc_ptr, wl.word_ids, wl.weights, device=0, bf16=True)
+    info = corpus.info
+    qs = [(np.ascontiguousarray(q, np.int32), np.ascontiguousarray(w, np.float32)) for q, w in wl.queries]
+    nq = len(qs)
+    lam, iters, N = sp.lam, sp.iters, info["N"]
+    # closed-loop capacity of both paths on a prefix, to place the arrival rate
+    nprobe = min(nq, 200)
+    for q, w in qs[:8]:
+        corpus.query(q, w, lam, iters)
+    t = time.perf_counter()
+    for q, w in qs[:nprobe]:
+        corpus.query(q, w, lam, iters)
+    plain_rate = nprobe / (time.perf_counter() - t)
+    print(f"# plain FP32 closed loop: {plain_rate:.1f} q/s", file=sys.stderr, flush=True)
+    budget = int(args.hbm_budget_gib * (1 << 30))
+    kw = dict(hbm_budget_bytes=budget, max_batch=args.max_batch, max_inflight=2,
+              precision=wmd.WMD_DIST_BF16)
+    with wmd.Server(corpus, **kw) as srv:
+        t = time.perf_counter()
+        ts = [srv.submit(q, w, lam, iters) for q, w in qs[:nprobe]]
+        for tk in ts:
+            srv.wait(tk)
+        served_rate = nprobe / (time.perf_counter() - t)
+    print(f"# served BF16 closed loop: {served_rate:.1f} q/s", file=sys.stderr, flush=True)
+    qps = args.qps if args.qps > 0 else 0.8 * plain_rate
+    arr = wl.arrivals[:nq] / qps          # unit-rate Poisson times scaled to the offered rate
+    with wmd.Server(corpus, **kw) as srv:
+        span = open_loop_served(srv, qs, arr, lam, iters)
+        st = srv.stats()
+    print(f"# served open loop done in {span:.1f} s", file=sys.stderr, flush=True)
+    lat_plain, span_plain = open_loop_plain(corpus, qs, arr, lam, iters)
+    print(f"# plain open loop done in {span_plain:.1f} s", file=sys.stderr, flush=True)
+    work = nq * N * iters
+    line = {
+        "metric": "served doc*iters/s + p50/p99 query latency",
+        "value": work / span, "unit": "doc*iters/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "bf16 distances, f32 Sinkhorn", "data": "synthetic",
+        "config": {"workload": f"{sp.name}: Poisson stream of {nq} queries, v_r log-uniform 3-500, "
+                               f"V={sp.V}, dim={sp.dim}, N={N}, nnz={info['nnz']}, U={info['U']}, "
+                               f"lambda={lam}, {iters} iterations",
+                   "qps": qps, "hbm_budget_bytes": budget, "max_batch": args.max_batch, "streams": 2},
+        "served": {"latency_ms": {"p50": st["latency_p50_ms"], "p99": st["latency_p99_ms"],
+                                  "mean": st["latency_mean_ms"], "max": st["latency_max_ms"]},
+                   "doc_iters_per_s": work / span, "mean_batch": st["mean_batch"],
+                   "closed_loop_qps": served_rate},
+        "plain_fp32": {"latency_ms": pct(lat_plain), "doc_iters_per_s": work / span_plain,
+                       "closed_loop_qps": plain_rate},
+    }
+    corpus.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -91,6 +267,9 @@ def main():
               "(documents would shard across GPUs with one all-gather of the N distances). "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.serve:
+        serve_main(args)
+        return
 
     import torch
     from paper_2005_06727_amd import synth, wmd
@@ -120,8 +299,9 @@ def main():
         step(i)
     torch.cuda.synchronize()
 
-    # timed region: K queries, kernel times from HIP events on each query's stream
-    wmd.wmd_set_timing(h, True)
+    # timed region: K queries; kernel times from HIP events on the query's
+    # stream, recorded on every 4th call (each event record costs a few us)
+    wmd.wmd_set_timing(h, 4)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -140,6 +320,15 @@ def main():
     torch.cuda.synchronize()
     iso = wmd.wmd_timing_get(h)
     wmd.wmd_set_timing(h, False)
+
+    if args.calibrate_copy > 0:
+        # a plain copy of known size: the profiler's byte counters read on it
+        # scale the counters read on the library's kernels
+        src = torch.ones(args.calibrate_copy << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     got = [o.cpu().numpy() for o in outs]
     assert all(np.all(np.isfinite(g)) and np.all(g > 0) for g in got)
@@ -188,7 +377,8 @@ def main():
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{sp.name}: 1 query (v_r={m}) vs N={N} docs, V={sp.V}, dim={dim}, "
-                               f"nnz={nnz}, U={U}, lambda={sp.lam}, {sp.iters} iterations, FP32 distances",
+                               f"nnz={nnz}, U={U}, lambda={sp.lam}, {sp.iters} iterations, FP32 distances; "
+                               f"consecutive queries on 2 streams",
                    "V": sp.V, "dim": dim, "N": N, "nnz": nnz, "U": U, "v_r": int(m), "lambda": sp.lam,
                    "iters": sp.iters, "parallelism": "single GPU"},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
@@ -200,6 +390,8 @@ def main():
         "streams": 2,
         "launches_per_step": tim["launches"],
     }
+    if not args.no_batch:
+        line["batch64"] = batch_section(wmd, corpus, sp)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, q, qw, args.cpu_seconds)
     corpus.close()

@@ -196,10 +196,12 @@ int wmd_query_batch_async(wmd_corpus* corpus, int32_t B, const int64_t* q_ptr,
                           double* dev_resid, void* stream);
 
 /*
- * Kernel timing, recorded with HIP events on the stream the kernels run on,
- * for every query or batch call made while timing is enabled.
- * wmd_set_timing(corpus, 1) enables it and clears the totals; 0 disables it.
- * wmd_timing_get waits for the recorded events and returns milliseconds.
+ * Kernel timing, recorded with HIP events on the stream the kernels run on.
+ * wmd_set_timing(corpus, k) with k > 0 clears the totals and records every
+ * k-th query or batch call from then on (1: every call; event records cost
+ * host and device time, so sparse sampling disturbs a pipeline less); 0
+ * disables it.  wmd_timing_get waits for the recorded events and returns
+ * milliseconds.  Errors: WMD_EINVAL for k < 0.
  */
 typedef struct wmd_timing {
     int64_t calls;            /* timed calls since timing was enabled */

@@ -82,6 +82,7 @@ void free_workspace(Workspace& w) {
     if (w.done) (void)hipEventDestroy(w.done);
     w.done = nullptr;
     w.done_valid = false;
+    w.last_stream = nullptr;
 }
 
 void free_staging(Staging& st) {
@@ -173,12 +174,14 @@ Layout make_layout(const wmd_corpus* c, const std::vector<PlannedQuery>& qs, con
     const int64_t row_tiles = (U + tile_rows - 1) / tile_rows;
     L.G = (int)std::max<int64_t>(1, std::min<int64_t>(B, (4096 + row_tiles - 1) / row_tiles));
     // parameter block: QueryDev[B] | qlist[B] | qgroup[G+1] | qid[sum_m] | r[sum_m] | rinv[sum_m]
-    L.off_ql = align_up(sizeof(QueryDev) * B, 256);
-    L.off_qg = align_up(L.off_ql + sizeof(int32_t) * B, 256);
-    L.off_id = align_up(L.off_qg + sizeof(int32_t) * (L.G + 1), 256);
-    L.off_r = align_up(L.off_id + sizeof(int32_t) * L.sum_m, 256);
-    L.off_ri = align_up(L.off_r + sizeof(float) * L.sum_m, 256);
-    L.pbytes = align_up(L.off_ri + sizeof(float) * L.sum_m, 256);
+    // (64-byte aligned sub-arrays: a one-query block stays small enough to
+    // travel as kernel arguments)
+    L.off_ql = align_up(sizeof(QueryDev) * B, 64);
+    L.off_qg = align_up(L.off_ql + sizeof(int32_t) * B, 64);
+    L.off_id = align_up(L.off_qg + sizeof(int32_t) * (L.G + 1), 64);
+    L.off_r = align_up(L.off_id + sizeof(int32_t) * L.sum_m, 64);
+    L.off_ri = align_up(L.off_r + sizeof(float) * L.sum_m, 64);
+    L.pbytes = align_up(L.off_ri + sizeof(float) * L.sum_m, 64);
     L.obytes = host_out ? sizeof(double) * (size_t)B * N * (resid ? 2 : 1) : 0;
     return L;
 }
@@ -334,8 +337,9 @@ int run_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_qu
     const int wslot = c->next_ws;
     c->next_ws = (c->next_ws + 1) % kWorkSlots;
     *slot_used = wslot;
-    return enqueue_queries(c, qs, opt, dev_out, dev_res, stream, need_host_out, c->ws[wslot], c->stage,
-                           c->timing);
+    // timing on: every c->timing-th call records its kernel events
+    const bool timed = c->timing > 0 && (c->timing_seq++ % c->timing) == 0;
+    return enqueue_queries(c, qs, opt, dev_out, dev_res, stream, need_host_out, c->ws[wslot], c->stage, timed);
 }
 
 size_t workspace_bytes(const wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_query_options& opt,
@@ -365,9 +369,19 @@ int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wm
         if (dev_res) dev_res = w.out + (size_t)B * N;
     }
 
-    int slot_s = 0;
-    if ((rc = take_staging(st, pbytes, &slot_s))) return rc;
-    char* hp = st.h[slot_s];
+    // small parameter blocks go up as kernel arguments (built in host memory
+    // here), larger ones through a pinned staging slot and a copy
+    const bool by_args = pbytes <= (size_t)kUploadMaxBytes;
+    thread_local std::vector<char> arg_block;
+    int slot_s = -1;
+    char* hp = nullptr;
+    if (by_args) {
+        arg_block.assign(pbytes, 0);
+        hp = arg_block.data();
+    } else {
+        if ((rc = take_staging(st, pbytes, &slot_s))) return rc;
+        hp = st.h[slot_s];
+    }
     char* dp = w.params;
     QueryDev* hq = reinterpret_cast<QueryDev*>(hp);
     int32_t* hql = reinterpret_cast<int32_t*>(hp + off_ql);
@@ -433,12 +447,18 @@ int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wm
     }
 
     hipError_t e;
-    if (w.done_valid && (e = hipStreamWaitEvent(stream, w.done, 0)) != hipSuccess)
+    // the slot's previous call must be done with its buffers; on the same
+    // stream that order holds already
+    if (w.done_valid && w.last_stream != stream && (e = hipStreamWaitEvent(stream, w.done, 0)) != hipSuccess)
         return hip_fail(e, "query: order after the slot's previous call");
-    if ((e = hipMemcpyAsync(dp, hp, pbytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
-        return hip_fail(e, "query: upload parameters");
-    if ((e = hipEventRecord(st.ev[slot_s], stream)) != hipSuccess) return hip_fail(e, "query: record");
-    st.pending[slot_s] = true;
+    if (by_args) {
+        if ((e = launch_upload(hp, pbytes, dp, stream)) != hipSuccess) return hip_fail(e, "query: upload parameters");
+    } else {
+        if ((e = hipMemcpyAsync(dp, hp, pbytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
+            return hip_fail(e, "query: upload parameters");
+        if ((e = hipEventRecord(st.ev[slot_s], stream)) != hipSuccess) return hip_fail(e, "query: record");
+        st.pending[slot_s] = true;
+    }
 
     const QueryDev* dq = reinterpret_cast<const QueryDev*>(dp);
     const int32_t* dql = reinterpret_cast<const int32_t*>(dp + off_ql);
@@ -495,6 +515,7 @@ int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wm
     }
     if ((e = hipEventRecord(w.done, stream)) != hipSuccess) return hip_fail(e, "query: record");
     w.done_valid = true;
+    w.last_stream = stream;
     return WMD_OK;
 }
 
@@ -821,7 +842,9 @@ int wmd_set_timing(wmd_corpus* c, int32_t enable) {
             if (e != hipSuccess) return hip_fail(e, "timing: wait");
             c->slot_pending[i] = false;
         }
-    c->timing = enable != 0;
+    if (enable < 0) return fail(WMD_EINVAL, "timing: enable must be >= 0");
+    c->timing = enable;
+    c->timing_seq = 0;
     c->timed_calls = 0;
     c->dist_ms_total = c->sink_ms_total = 0.0;
     c->last_dist_ms = c->last_sink_ms = 0.f;

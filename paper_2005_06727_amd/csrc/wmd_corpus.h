@@ -38,6 +38,7 @@ struct Workspace {
     size_t hocap = 0;
     hipEvent_t done = nullptr;
     bool done_valid = false;
+    hipStream_t last_stream = nullptr;   // stream of the slot's previous call
     bool carved = false;      // buffers point into memory owned elsewhere (fixed capacity)
 };
 constexpr int kWorkSlots = 2;
@@ -101,7 +102,8 @@ struct wmd_corpus {
     hipEvent_t ev[kTimingSlots][3] = {};
     bool slot_pending[kTimingSlots] = {};
     int next_slot = 0, last_slot = -1;
-    bool timing = false;
+    int32_t timing = 0;                 // 0: off; k: record every k-th call
+    int64_t timing_seq = 0;
     int64_t timed_calls = 0;
     double dist_ms_total = 0.0, sink_ms_total = 0.0;
     float last_dist_ms = 0.f, last_sink_ms = 0.f;

@@ -74,6 +74,11 @@ hipError_t launch_prep_norms(const float* rows, int64_t nrows, int ldv, float* n
 hipError_t launch_prep_bf16(const float* src, uint16_t* dst, float* norms, int64_t nrows, int ldv,
                             hipStream_t s);
 hipError_t launch_prep_docs(const int32_t* ptr, const float* w, float* cw, int64_t N, hipStream_t s);
+// Parameter blocks up to kUploadMaxBytes are uploaded as kernel arguments, in
+// chunks of kUploadChunkBytes (one small launch each).
+constexpr int kUploadChunkBytes = 2048;
+constexpr int kUploadMaxBytes = 4 * kUploadChunkBytes;
+hipError_t launch_upload(const void* src, size_t bytes, void* dst, hipStream_t s);
 hipError_t launch_gather_rows(const float* vecs, const int32_t* ids, float* out, int64_t nrows, int ldv,
                               hipStream_t s);
 

@@ -264,8 +264,9 @@ def wmd_query_batch_async(corpus: int, queries, lambdas, iters, dev_dist, dev_re
                                       C.byref(o), _devptr(dev_dist), _devptr(dev_resid), _stream(stream)))
 
 
-def wmd_set_timing(corpus: int, enable: bool) -> None:
-    _check(_lib.wmd_set_timing(corpus, int(bool(enable))))
+def wmd_set_timing(corpus: int, every) -> None:
+    """every: False/0 off, True/1 every call, k: every k-th call."""
+    _check(_lib.wmd_set_timing(corpus, int(every)))
 
 
 def wmd_timing_get(corpus: int) -> dict:
