@@ -381,8 +381,9 @@ def main():
                                f"consecutive queries on 2 streams",
                    "V": sp.V, "dim": dim, "N": N, "nnz": nnz, "U": U, "v_r": int(m), "lambda": sp.lam,
                    "iters": sp.iters, "parallelism": "single GPU"},
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "what": "synchronous wmd_query: host query in, host distances out"},
+        "latency_ms": ({"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                        "what": "synchronous wmd_query: host query in, host distances out"}
+                       if lat.size else None),
         "roofline": roofline,
         "kernels": kernels,
         "kernels_isolated_us": {"dist_gemm": iso["dist_ms"] / max(iso["calls"], 1) * 1e3,
