@@ -70,6 +70,28 @@ __device__ __forceinline__ float sum_over_b(float v) {
 // Sum over the R lanes with the same b (lane stride C) of an R*C-lane team.
 // Every step pairs lane l with lane l ^ o; IEEE addition is commutative, so
 // both partners get the same bits and the R copies of x stay identical.
+// sum_over_b for K values at once, step-major so that no DPP op reads a
+// value written by the instruction just before it
+template <int C, int K>
+__device__ __forceinline__ void sum_over_b_n(float* v) {
+    if constexpr (C >= 2) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] += dpp<0xB1>(v[k]);
+    }
+    if constexpr (C >= 4) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] += dpp<0x4E>(v[k]);
+    }
+    if constexpr (C >= 8) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] += dpp<0x141>(v[k]);
+    }
+    if constexpr (C >= 16) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] += dpp<0x140>(v[k]);
+    }
+}
+
 template <int R, int C>
 __device__ __forceinline__ float sum_over_a(float v) {
     constexpr int T = R * C;
@@ -80,6 +102,37 @@ __device__ __forceinline__ float sum_over_a(float v) {
     if constexpr (T > 16) v = add_xor16(v);              // lane ^ 16
     if constexpr (T > 32) v = add_xor32(v);              // lane ^ 32
     return v;
+}
+
+// Sum over the 4 lane rows (lanes l, l^16, l^32, l^48) of four values at once:
+// a reduce-scatter with the gfx950 row swaps leaves row j of t with one of the
+// four sums (each computed once), then the swaps copy every sum to every row,
+// so all copies carry identical bits.  12 VALU ops for 4 values, against 24
+// for four separate xor16 + xor32 butterflies.
+__device__ __forceinline__ void sum_rows4(float& y0, float& y1, float& y2, float& y3) {
+    auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(y0), __float_as_uint(y1), false, false);
+    const float s01 = __uint_as_float(a[0]) + __uint_as_float(a[1]);   // rows 0-1: y0, rows 2-3: y1
+    auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(y2), __float_as_uint(y3), false, false);
+    const float s23 = __uint_as_float(b[0]) + __uint_as_float(b[1]);   // rows 0-1: y2, rows 2-3: y3
+    auto c = __builtin_amdgcn_permlane16_swap(__float_as_uint(s01), __float_as_uint(s23), false, false);
+    const float t = __uint_as_float(c[0]) + __uint_as_float(c[1]);     // rows 0,1,2,3: y0,y2,y1,y3
+    auto d = __builtin_amdgcn_permlane16_swap(__float_as_uint(t), __float_as_uint(t), false, false);
+    // d[0]: rows (0,0,2,2) of t = (y0,y0,y1,y1); d[1]: rows (1,1,3,3) = (y2,y2,y3,y3)
+    auto e = __builtin_amdgcn_permlane32_swap(d[0], d[0], false, false);
+    auto f = __builtin_amdgcn_permlane32_swap(d[1], d[1], false, false);
+    y0 = __uint_as_float(e[0]);
+    y1 = __uint_as_float(e[1]);
+    y2 = __uint_as_float(f[0]);
+    y3 = __uint_as_float(f[1]);
+}
+
+// ln k for a kernel value 0 < k <= 1 with the hardware log2 (inputs below
+// 2^-64 are scaled first, as the hardware op does not take denormals).  Its
+// absolute error (about 2^-22) enters M = n - ln(k) / lambda divided by lambda.
+__device__ __forceinline__ float ln_k(float k) {
+    const bool tiny = k < 0x1p-64f;
+    const float l2 = __builtin_amdgcn_logf(tiny ? k * 0x1p64f : k) - (tiny ? 64.f : 0.f);
+    return l2 * 0.693147180559945309f;
 }
 
 template <int T>
@@ -97,14 +150,227 @@ __device__ __forceinline__ int wave_max(int v) {
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// One team's work on its document with PN rows per lane (PN a multiple of 4,
+// fixed at compile time so the code is straight-line; the kernel picks PN per
+// wave from the longest document of the wave).
+template <int R, int C, int P, int Q, int W, int PN>
+__device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp, const bool valid, const int d,
+                                          const int rs, const int n, const int m, const int ldk, const int a,
+                                          const int b, const int tl, const int wi, const int team, const int kb,
+                                          const int it_end, const int my_end, float* s_part, double* s_red) {
+    constexpr int T = R * C;
+    constexpr int Q4 = Q / 4;
+
+    // A and every per-row / per-column vector are zero outside the document's
+    // n x m block; padded rows get s + 1 and padded columns x = 1, so the
+    // reciprocals stay finite and the arithmetic needs no per-element guards
+    float A[PN][Q];
+    float cval[PN], spad[PN];
+#pragma unroll
+    for (int p = 0; p < PN; ++p) {
+        const int i = a + R * p;
+        const bool row = valid && i < n;
+        cval[p] = row ? g.scw[rs + i] : 0.f;
+        spad[p] = row ? 0.f : 1.f;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) A[p][q] = 0.f;
+        if (row) {
+            const float* rowp = qp->Kt + (int64_t)g.scol[rs + i] * ldk;
+#pragma unroll
+            for (int q4 = 0; q4 < Q4; ++q4) {
+                const int k0 = kb + 4 * q4;
+                if (k0 < m) {
+                    const float4 t = *reinterpret_cast<const float4*>(rowp + k0);
+                    A[p][4 * q4 + 0] = t.x;
+                    A[p][4 * q4 + 1] = (k0 + 1 < m) ? t.y : 0.f;
+                    A[p][4 * q4 + 2] = (k0 + 2 < m) ? t.z : 0.f;
+                    A[p][4 * q4 + 3] = (k0 + 3 < m) ? t.w : 0.f;
+                }
+            }
+        }
+    }
+
+    float x[Q], rinv[Q], xpad[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int k = kb + q;
+        const bool kv = k < m;
+        rinv[q] = kv ? qp->rinv[k] : 0.f;
+        xpad[q] = kv ? 0.f : 1.f;
+        if (g.it_begin == 0) x[q] = kv ? 1.0f / (float)m : 1.f;
+        else x[q] = kv ? qp->x[(int64_t)d * ldk + k] : 1.f;
+    }
+
+    float u[Q], s[PN], v[PN], y[Q];
+    int par = 0;
+
+    // s = A u summed over the team (lanes b, then waves); v = c / s
+    auto sddmm = [&](void) {
+#pragma unroll
+        for (int p = 0; p < PN; ++p) {
+            float acc = A[p][0] * u[0];
+#pragma unroll
+            for (int q = 1; q < Q; ++q) acc = fmaf(A[p][q], u[q], acc);
+            s[p] = acc;
+        }
+        sum_over_b_n<C, PN>(s);
+        if constexpr (W > 1) {
+            float* sp = s_part + ((team * 2 + par) * W) * (R * P);
+            if (b == 0) {
+#pragma unroll
+                for (int p = 0; p < PN; ++p) sp[wi * R * P + a + R * p] = s[p];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int p = 0; p < PN; ++p) {
+                float t = 0.f;
+                for (int w2 = 0; w2 < W; ++w2) t += sp[w2 * R * P + a + R * p];
+                s[p] = t;
+            }
+            par ^= 1;
+        }
+#pragma unroll
+        for (int p = 0; p < PN; ++p) v[p] = cval[p] * rcp(s[p] + spad[p]);
+    };
+
+    // y = A^T v summed over the team's rows (lanes a)
+    auto spmm = [&](void) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) y[q] = A[0][q] * v[0];
+#pragma unroll
+        for (int p = 1; p < PN; ++p) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) y[q] = fmaf(A[p][q], v[p], y[q]);
+        }
+        if constexpr (R == 4 && C == 16 && Q % 4 == 0) {
+#pragma unroll
+            for (int q = 0; q < Q; q += 4) sum_rows4(y[q], y[q + 1], y[q + 2], y[q + 3]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) y[q] = sum_over_a<R, C>(y[q]);
+        }
+    };
+
+    for (int it = g.it_begin; it < it_end; ++it) {
+        if constexpr (W == 1) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) u[q] = rcp(x[q]);
+            sddmm();
+            spmm();
+#pragma unroll
+            for (int q = 0; q < Q; ++q) x[q] = fmaf(y[q], rinv[q], xpad[q]);
+        } else {
+            // teams of a block run the block's largest iteration count (same
+            // barriers); a team past its own count computes but keeps x
+            const bool act = it < my_end;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) u[q] = rcp(x[q]);
+            sddmm();
+            spmm();
+            if (act) {
+#pragma unroll
+                for (int q = 0; q < Q; ++q) x[q] = fmaf(y[q], rinv[q], xpad[q]);
+            }
+        }
+    }
+
+    if (!g.final_step) {
+        if (valid && a == 0) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+                if (kb + q < m) qp->x[(int64_t)d * ldk + kb + q] = x[q];
+        }
+        return;
+    }
+
+    // final step: u = 1/x (0 on padded columns), v = c / (K^T u)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) u[q] = (xpad[q] == 0.f) ? rcp(x[q]) : 0.f;
+    sddmm();
+
+    double rho = 0.0;
+    const bool want_resid = valid && qp->resid != nullptr;
+    if (__builtin_amdgcn_readfirstlane((int)(qp->resid != nullptr))) {
+        spmm();
+        if (want_resid && a == 0) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+                if (kb + q < m) rho += fabs((double)u[q] * (double)y[q] - (double)qp->r[kb + q]);
+        }
+    }
+
+    // WMD = sum_i v_i sum_k (K .* M)[i][k] u_k: FP32 products, FP64 sum.  K .* M
+    // is rebuilt from the K block in registers (M = n_i - ln K / lambda) or
+    // gathered from KMt when lambda is too small for that.
+    double wsum = 0.0;
+    if (qp->km_from_k) {
+        const float il = qp->inv_lambda;
+#pragma unroll
+        for (int p = 0; p < PN; ++p) {
+            const int i = a + R * p;
+            const float nr = (qp->nrow && valid && i < n) ? qp->nrow[g.scol[rs + i]] : 0.f;
+            const double vp = (double)v[p];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const float kk = A[p][q];
+                const float km = (kk > 0.f) ? kk * (nr - ln_k(kk) * il) : 0.f;
+                wsum = fma((double)(km * u[q]), vp, wsum);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int p = 0; p < PN; ++p) {
+            const int i = a + R * p;
+            if (valid && i < n) {
+                const float* row = qp->KMt + (int64_t)g.scol[rs + i] * ldk;
+                const double vp = (double)v[p];
+#pragma unroll
+                for (int q4 = 0; q4 < Q4; ++q4) {
+                    const int k0 = kb + 4 * q4;
+                    if (k0 < m) {
+                        float4 t = *reinterpret_cast<const float4*>(row + k0);
+                        // u is zero beyond m, so the padded columns add nothing
+                        wsum = fma((double)(t.x * u[4 * q4 + 0]), vp, wsum);
+                        wsum = fma((double)(t.y * u[4 * q4 + 1]), vp, wsum);
+                        wsum = fma((double)(t.z * u[4 * q4 + 2]), vp, wsum);
+                        wsum = fma((double)(t.w * u[4 * q4 + 3]), vp, wsum);
+                    }
+                }
+            }
+        }
+    }
+    wsum = team_sum_f64<T>(wsum);
+    if (__builtin_amdgcn_readfirstlane((int)(qp->resid != nullptr))) rho = team_sum_f64<T>(rho);
+    if constexpr (W > 1) {
+        if (tl == 0) {
+            s_red[(team * W + wi) * 2 + 0] = wsum;
+            s_red[(team * W + wi) * 2 + 1] = rho;
+        }
+        __syncthreads();
+        if (wi == 0 && tl == 0) {
+            wsum = 0.0;
+            rho = 0.0;
+            for (int w2 = 0; w2 < W; ++w2) {
+                wsum += s_red[(team * W + w2) * 2 + 0];
+                rho += s_red[(team * W + w2) * 2 + 1];
+            }
+        }
+    }
+    if (valid && tl == 0 && wi == 0) {
+        const int doc = g.sdoc[d];
+        qp->out[doc] = wsum;
+        if (want_resid) qp->resid[doc] = rho;
+    }
+}
+
 template <int R, int C, int P, int Q, int W>
 __global__ __launch_bounds__(256) void k_sink(SinkArgs g) {
     constexpr int T = R * C;
     static_assert(W == 1 || T == 64, "multi-wave teams use whole waves");
     static_assert(Q % 4 == 0, "columns are loaded as float4");
+    static_assert(P % 4 == 0, "rows come in groups of 4");
     constexpr int TPW = 64 / T;
     constexpr int TEAMS = (W == 1) ? 4 * TPW : 4 / W;
-    constexpr int Q4 = Q / 4;
 
     __shared__ float s_part[(W > 1) ? TEAMS * 2 * W * R * P : 1];
     __shared__ double s_red[(W > 1) ? TEAMS * W * 2 : 1];
@@ -131,52 +397,6 @@ __global__ __launch_bounds__(256) void k_sink(SinkArgs g) {
     const int n = valid ? g.sptr[d + 1] - rs : 0;
     const int kb = (wi * C + b) * Q;
 
-    // row blocks in use, uniform over the wave (documents of a launch are sorted
-    // by length, so the teams of a wave have similar n); held in an SGPR
-    const int pn = __builtin_amdgcn_readfirstlane(wave_max((n + R - 1) / R));
-
-    // A and every per-column / per-row vector are zero outside the document's
-    // n x m block, so the arithmetic below needs no per-element guards
-    float A[P][Q];
-    float cval[P];
-    bool kval[Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) kval[q] = kb + q < m;
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-        cval[p] = 0.f;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) A[p][q] = 0.f;
-    }
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-        const int i = a + R * p;
-        if (p < pn && i < n) {
-            cval[p] = g.scw[rs + i];
-            const float* row = qp->Kt + (int64_t)g.scol[rs + i] * ldk;
-#pragma unroll
-            for (int q4 = 0; q4 < Q4; ++q4) {
-                const int k0 = kb + 4 * q4;
-                if (k0 < m) {
-                    float4 t = *reinterpret_cast<const float4*>(row + k0);
-                    A[p][4 * q4 + 0] = t.x;
-                    A[p][4 * q4 + 1] = kval[4 * q4 + 1] ? t.y : 0.f;
-                    A[p][4 * q4 + 2] = kval[4 * q4 + 2] ? t.z : 0.f;
-                    A[p][4 * q4 + 3] = kval[4 * q4 + 3] ? t.w : 0.f;
-                }
-            }
-        }
-    }
-
-    float x[Q], rinv[Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const int k = kb + q;
-        rinv[q] = kval[q] ? qp->rinv[k] : 0.f;
-        if (g.it_begin == 0) x[q] = kval[q] ? 1.0f / (float)m : 1.f;
-        else x[q] = kval[q] ? qp->x[(int64_t)d * ldk + k] : 1.f;
-    }
-
     int it_end = valid ? min(g.it_begin + g.it_count, qp->iters) : g.it_begin;
     if constexpr (W > 1) {
         // every wave of the block must run the same number of barriers
@@ -191,164 +411,23 @@ __global__ __launch_bounds__(256) void k_sink(SinkArgs g) {
     }
     const int my_end = valid ? min(g.it_begin + g.it_count, qp->iters) : g.it_begin;
 
-    float u[Q], s[P], v[P];
-#pragma unroll
-    for (int p = 0; p < P; ++p) s[p] = 0.f;
-    int par = 0;
-
-    // s = A u summed over the team (lanes b, then waves); v = c / s
-    auto sddmm = [&](void) {
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-            if (p < pn) {
-                float acc = 0.f;
-#pragma unroll
-                for (int q = 0; q < Q; ++q) acc = fmaf(A[p][q], u[q], acc);
-                s[p] = acc;
-            }
-        }
-        // rows p >= pn hold zeros; reducing them too lets the reductions interleave
-#pragma unroll
-        for (int p = 0; p < P; ++p) s[p] = sum_over_b<C>(s[p]);
-        if constexpr (W > 1) {
-            float* sp = s_part + ((team * 2 + par) * W) * (R * P);
-            if (b == 0) {
-#pragma unroll
-                for (int p = 0; p < P; ++p)
-                    if (p < pn) sp[wi * R * P + a + R * p] = s[p];
-            }
-            __syncthreads();
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-                if (p < pn) {
-                    float t = 0.f;
-                    for (int w2 = 0; w2 < W; ++w2) t += sp[w2 * R * P + a + R * p];
-                    s[p] = t;
-                }
-            }
-            par ^= 1;
-        }
-#pragma unroll
-        for (int p = 0; p < P; ++p) v[p] = (cval[p] > 0.f) ? cval[p] * rcp(s[p]) : 0.f;
-    };
-
-    // y = A^T v summed over the team's rows (lanes a)
-    float y[Q];
-    auto spmm = [&](void) {
-#pragma unroll
-        for (int q = 0; q < Q; ++q) y[q] = 0.f;
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-            if (p < pn) {
-#pragma unroll
-                for (int q = 0; q < Q; ++q) y[q] = fmaf(A[p][q], v[p], y[q]);
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < Q; ++q) y[q] = sum_over_a<R, C>(y[q]);
-    };
-
-    for (int it = g.it_begin; it < it_end; ++it) {
-        const bool act = it < my_end;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) u[q] = (act && kval[q]) ? rcp(x[q]) : 0.f;
-        sddmm();
-        spmm();
-        if (act) {
-#pragma unroll
-            for (int q = 0; q < Q; ++q) x[q] = y[q] * rinv[q];
-        }
-    }
-
-    if (!g.final_step) {
-        if (valid && a == 0) {
-#pragma unroll
-            for (int q = 0; q < Q; ++q)
-                if (kb + q < m) qp->x[(int64_t)d * ldk + kb + q] = x[q];
-        }
-        return;
-    }
-
-    // final step: u = 1/x, v = c / (K^T u)
-#pragma unroll
-    for (int q = 0; q < Q; ++q) u[q] = kval[q] ? rcp(x[q]) : 0.f;
-    sddmm();
-
-    double rho = 0.0;
-    const bool want_resid = valid && qp->resid != nullptr;
-    if (__builtin_amdgcn_readfirstlane((int)(qp->resid != nullptr))) {
-        spmm();
-        if (want_resid && a == 0) {
-#pragma unroll
-            for (int q = 0; q < Q; ++q)
-                if (kval[q]) rho += fabs((double)u[q] * (double)y[q] - (double)qp->r[kb + q]);
-        }
-    }
-
-    // WMD = sum_i v_i sum_k (K .* M)[i][k] u_k: FP32 products, FP64 sum.  K .* M
-    // is rebuilt from the K block in registers (M = n_i - ln K / lambda) or
-    // gathered from KMt when lambda is too small for that.
-    double wsum = 0.0;
-    if (qp->km_from_k) {
-        const float il = qp->inv_lambda;
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-            if (p < pn) {
-                const int i = a + R * p;
-                const float nr = (qp->nrow && i < n) ? qp->nrow[g.scol[rs + i]] : 0.f;
-                const double vp = (double)v[p];
-#pragma unroll
-                for (int q = 0; q < Q; ++q) {
-                    const float kk = A[p][q];
-                    const float km = (kk > 0.f) ? kk * (nr - logf(kk) * il) : 0.f;
-                    wsum = fma((double)(km * u[q]), vp, wsum);
-                }
-            }
-        }
+    // rows per lane for this wave, in groups of 4 (documents of a launch are
+    // sorted by length, so the teams of a wave have similar n); uniform, SGPR
+    const int pg = __builtin_amdgcn_readfirstlane((wave_max((n + R - 1) / R) + 3) >> 2);
+#define WMD_SINK_TEAM(PN) \
+    sink_team<R, C, P, Q, W, PN>(g, qp, valid, d, rs, n, m, ldk, a, b, tl, wi, team, kb, it_end, my_end, s_part, s_red)
+    if constexpr (P == 16) {
+        if (pg <= 1) WMD_SINK_TEAM(4);
+        else if (pg == 2) WMD_SINK_TEAM(8);
+        else if (pg == 3) WMD_SINK_TEAM(12);
+        else WMD_SINK_TEAM(16);
+    } else if constexpr (P == 8) {
+        if (pg <= 1) WMD_SINK_TEAM(4);
+        else WMD_SINK_TEAM(8);
     } else {
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-            const int i = a + R * p;
-            if (p < pn && i < n) {
-                const float* row = qp->KMt + (int64_t)g.scol[rs + i] * ldk;
-                const double vp = (double)v[p];
-#pragma unroll
-                for (int q4 = 0; q4 < Q4; ++q4) {
-                    const int k0 = kb + 4 * q4;
-                    if (k0 < m) {
-                        float4 t = *reinterpret_cast<const float4*>(row + k0);
-                        // u is zero beyond m, so the padded columns add nothing
-                        wsum = fma((double)(t.x * u[4 * q4 + 0]), vp, wsum);
-                        wsum = fma((double)(t.y * u[4 * q4 + 1]), vp, wsum);
-                        wsum = fma((double)(t.z * u[4 * q4 + 2]), vp, wsum);
-                        wsum = fma((double)(t.w * u[4 * q4 + 3]), vp, wsum);
-                    }
-                }
-            }
-        }
+        WMD_SINK_TEAM(P);
     }
-    wsum = team_sum_f64<T>(wsum);
-    rho = team_sum_f64<T>(rho);
-    if constexpr (W > 1) {
-        if (tl == 0) {
-            s_red[(team * W + wi) * 2 + 0] = wsum;
-            s_red[(team * W + wi) * 2 + 1] = rho;
-        }
-        __syncthreads();
-        if (wi == 0 && tl == 0) {
-            wsum = 0.0;
-            rho = 0.0;
-            for (int w2 = 0; w2 < W; ++w2) {
-                wsum += s_red[(team * W + w2) * 2 + 0];
-                rho += s_red[(team * W + w2) * 2 + 1];
-            }
-        }
-    }
-    if (valid && tl == 0 && wi == 0) {
-        const int doc = g.sdoc[d];
-        qp->out[doc] = wsum;
-        if (want_resid) qp->resid[doc] = rho;
-    }
+#undef WMD_SINK_TEAM
 }
 
 // Any size: one 256-thread block per (query, document); the K block is
@@ -418,7 +497,7 @@ __global__ __launch_bounds__(256) void k_sink_stream(SinkArgs g) {
             const float nr = qp->nrow ? qp->nrow[col] : 0.f, il = qp->inv_lambda;
             for (int k = 0; k < m; ++k) {
                 const float kk = row[k];
-                const float km = (kk > 0.f) ? kk * (nr - logf(kk) * il) : 0.f;
+                const float km = (kk > 0.f) ? kk * (nr - ln_k(kk) * il) : 0.f;
                 wsum = fma((double)(km * u[k]), vi, wsum);
             }
         } else {
@@ -427,7 +506,7 @@ __global__ __launch_bounds__(256) void k_sink_stream(SinkArgs g) {
         }
     }
     wsum = team_sum_f64<64>(wsum);
-    rho = team_sum_f64<64>(rho);
+    if (qp->resid) rho = team_sum_f64<64>(rho);
     if ((tid & 63) == 0) {
         red[0][tid >> 6] = wsum;
         red[1][tid >> 6] = rho;
@@ -578,7 +657,7 @@ __global__ __launch_bounds__(64) void k_sink_rows(SinkArgs g) {
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         const float kk = A[r][4 * k4 + e];
-                        const float km = (kk > 0.f) ? kk * (nr - logf(kk) * il) : 0.f;
+                        const float km = (kk > 0.f) ? kk * (nr - ln_k(kk) * il) : 0.f;
                         wsum = fma((double)(km * ue[e]), vr, wsum);
                     }
                 }
@@ -600,7 +679,7 @@ __global__ __launch_bounds__(64) void k_sink_rows(SinkArgs g) {
         }
     }
     wsum = team_sum_f64<64>(wsum);
-    rho = team_sum_f64<64>(rho);
+    if (qp->resid) rho = team_sum_f64<64>(rho);
     (void)red;
     if (lane == 0) {
         const int doc = g.sdoc[d];
