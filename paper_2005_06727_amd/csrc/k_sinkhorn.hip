@@ -135,6 +135,59 @@ __device__ __forceinline__ float ln_k(float k) {
     return l2 * 0.693147180559945309f;
 }
 
+// Lane-pair sums of two values at once over lane ^ 16 (ROW = 16) or lane ^ 32
+// (ROW = 32): a swap leaves one value's pair sum in each half, a second swap
+// copies both sums to both halves (each sum computed once, identical bits).
+template <int ROW>
+__device__ __forceinline__ void pair_sum2(float& y0, float& y1) {
+    auto swp = [](uint32_t a, uint32_t b) {
+        if constexpr (ROW == 16) return __builtin_amdgcn_permlane16_swap(a, b, false, false);
+        else return __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    };
+    auto r = swp(__float_as_uint(y0), __float_as_uint(y1));
+    const float t = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    auto e = swp(__float_as_uint(t), __float_as_uint(t));
+    y0 = __uint_as_float(e[0]);
+    y1 = __uint_as_float(e[1]);
+}
+
+// sum_over_a for K values at once, step-major; K even
+template <int R, int C, int K>
+__device__ __forceinline__ void sum_over_a_n(float* y) {
+    constexpr int T = R * C;
+    if constexpr (C <= 1 && T > 1) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) y[k] += dpp<0xB1>(y[k]);
+    }
+    if constexpr (C <= 2 && T > 2) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) y[k] += dpp<0x4E>(y[k]);
+    }
+    if constexpr (C <= 4 && T > 4) {
+        // lane ^ 4 through the LDS crossbar (no LDS memory, no VALU slot)
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            y[k] += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(y[k]), 0x101F));
+    }
+    if constexpr (C <= 8 && T > 8) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) y[k] += dpp<0x128>(y[k]);
+    }
+    if constexpr (T == 64 && K % 4 == 0) {
+#pragma unroll
+        for (int k = 0; k < K; k += 4) sum_rows4(y[k], y[k + 1], y[k + 2], y[k + 3]);
+    } else {
+        if constexpr (T > 16) {
+#pragma unroll
+            for (int k = 0; k < K; k += 2) pair_sum2<16>(y[k], y[k + 1]);
+        }
+        if constexpr (T > 32) {
+#pragma unroll
+            for (int k = 0; k < K; k += 2) pair_sum2<32>(y[k], y[k + 1]);
+        }
+    }
+}
+
 template <int T>
 __device__ __forceinline__ double team_sum_f64(double v) {
 #pragma unroll
@@ -162,18 +215,20 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
     constexpr int Q4 = Q / 4;
 
     // A and every per-row / per-column vector are zero outside the document's
-    // n x m block; padded rows get s + 1 and padded columns x = 1, so the
-    // reciprocals stay finite and the arithmetic needs no per-element guards
+    // n x m block, except that a padded row holds 1 in column 0 (which every
+    // query has) and a padded column keeps x = 1: the reciprocals stay finite,
+    // padded rows get v = 0 and padded columns add nothing, so the arithmetic
+    // needs no per-element guards
     float A[PN][Q];
-    float cval[PN], spad[PN];
+    float cval[PN];
 #pragma unroll
     for (int p = 0; p < PN; ++p) {
         const int i = a + R * p;
         const bool row = valid && i < n;
         cval[p] = row ? g.scw[rs + i] : 0.f;
-        spad[p] = row ? 0.f : 1.f;
 #pragma unroll
         for (int q = 0; q < Q; ++q) A[p][q] = 0.f;
+        if (!row && kb == 0) A[p][0] = 1.f;
         if (row) {
             const float* rowp = qp->Kt + (int64_t)g.scol[rs + i] * ldk;
 #pragma unroll
@@ -205,6 +260,8 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
     int par = 0;
 
     // s = A u summed over the team (lanes b, then waves); v = c / s
+    // (the scheduling barriers keep each phase step-major: every reduction step
+    // and reciprocal then has independent work between it and its consumer)
     auto sddmm = [&](void) {
 #pragma unroll
         for (int p = 0; p < PN; ++p) {
@@ -213,7 +270,9 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
             for (int q = 1; q < Q; ++q) acc = fmaf(A[p][q], u[q], acc);
             s[p] = acc;
         }
+        __builtin_amdgcn_sched_barrier(0);
         sum_over_b_n<C, PN>(s);
+        __builtin_amdgcn_sched_barrier(0);
         if constexpr (W > 1) {
             float* sp = s_part + ((team * 2 + par) * W) * (R * P);
             if (b == 0) {
@@ -230,7 +289,10 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
             par ^= 1;
         }
 #pragma unroll
-        for (int p = 0; p < PN; ++p) v[p] = cval[p] * rcp(s[p] + spad[p]);
+        for (int p = 0; p < PN; ++p) s[p] = rcp(s[p]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int p = 0; p < PN; ++p) v[p] = cval[p] * s[p];
     };
 
     // y = A^T v summed over the team's rows (lanes a)
@@ -242,13 +304,9 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
 #pragma unroll
             for (int q = 0; q < Q; ++q) y[q] = fmaf(A[p][q], v[p], y[q]);
         }
-        if constexpr (R == 4 && C == 16 && Q % 4 == 0) {
-#pragma unroll
-            for (int q = 0; q < Q; q += 4) sum_rows4(y[q], y[q + 1], y[q + 2], y[q + 3]);
-        } else {
-#pragma unroll
-            for (int q = 0; q < Q; ++q) y[q] = sum_over_a<R, C>(y[q]);
-        }
+        __builtin_amdgcn_sched_barrier(0);
+        sum_over_a_n<R, C, Q>(y);
+        __builtin_amdgcn_sched_barrier(0);
     };
 
     for (int it = g.it_begin; it < it_end; ++it) {
