@@ -168,17 +168,12 @@ Layout make_layout(const wmd_corpus* c, const std::vector<PlannedQuery>& qs, con
     L.kmfloats = any_km ? L.kfloats : 0;
     L.xfloats = L.chunked ? (size_t)N * L.sum_ldk : 0;
     L.nfloats = opt.log_domain ? (size_t)U * B : 0;
-    // distance-kernel groups: contiguous runs of queries with balanced column counts,
-    // enough of them that row tiles x groups fills the device
-    const int64_t tile_rows = opt.precision == WMD_DIST_BF16 ? 64 : 32;
-    const int64_t row_tiles = (U + tile_rows - 1) / tile_rows;
-    L.G = (int)std::max<int64_t>(1, std::min<int64_t>(B, (4096 + row_tiles - 1) / row_tiles));
-    // parameter block: QueryDev[B] | qlist[B] | qgroup[G+1] | qid[sum_m] | r[sum_m] | rinv[sum_m]
+    // parameter block: QueryDev[B] | qlist[B] | kofs[B+1] | qid[sum_m] | r[sum_m] | rinv[sum_m]
     // (64-byte aligned sub-arrays: a one-query block stays small enough to
     // travel as kernel arguments)
     L.off_ql = align_up(sizeof(QueryDev) * B, 64);
     L.off_qg = align_up(L.off_ql + sizeof(int32_t) * B, 64);
-    L.off_id = align_up(L.off_qg + sizeof(int32_t) * (L.G + 1), 64);
+    L.off_id = align_up(L.off_qg + sizeof(int32_t) * (B + 1), 64);
     L.off_r = align_up(L.off_id + sizeof(int32_t) * L.sum_m, 64);
     L.off_ri = align_up(L.off_r + sizeof(float) * L.sum_m, 64);
     L.pbytes = align_up(L.off_ri + sizeof(float) * L.sum_m, 64);
@@ -354,7 +349,7 @@ int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wm
     const int B = (int)qs.size();
     const int64_t N = dc.N, U = dc.U;
     const Layout L = make_layout(c, qs, opt, dev_res != nullptr, need_host_out);
-    const int max_m = L.max_m, max_iters = L.max_iters, per_launch = L.per_launch, G = L.G;
+    const int max_m = L.max_m, max_iters = L.max_iters, per_launch = L.per_launch;
     const bool chunked = L.chunked;
     const size_t sum_ldk = L.sum_ldk;
     const size_t off_ql = L.off_ql, off_qg = L.off_qg, off_id = L.off_id, off_r = L.off_r, off_ri = L.off_ri;
@@ -418,17 +413,8 @@ int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wm
         ko += q.ldk;
         mo += q.m;
     }
-    {
-        hqg[0] = 0;
-        int g = 1;
-        size_t acc = 0;
-        for (int b = 0; b < B && g < G; ++b) {
-            acc += qs[b].ldk;
-            if (acc * G >= sum_ldk * g && B - (b + 1) >= G - g) hqg[g++] = b + 1;
-        }
-        while (g < G) { hqg[g] = hqg[g - 1] + 1; ++g; }   // not reached when B >= G
-        hqg[G] = B;
-    }
+    hqg[0] = 0;   // kofs: first global distance-GEMM column of each query
+    for (int b = 0; b < B; ++b) hqg[b + 1] = hqg[b] + qs[b].ldk;
     // group queries by Sinkhorn launch shape: streaming-only first, then each register shape
     std::vector<int> shape_of(B);
     const int nshape = sinkhorn_num_shapes();
@@ -451,8 +437,12 @@ int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wm
     // stream that order holds already
     if (w.done_valid && w.last_stream != stream && (e = hipStreamWaitEvent(stream, w.done, 0)) != hipSuccess)
         return hip_fail(e, "query: order after the slot's previous call");
+    // one short query: its parameters ride along with the distance kernel
+    const int bf16 = opt.precision == WMD_DIST_BF16 ? 1 : 0;
+    const bool narrow = by_args && dist_narrow_fits(dc, bf16, B, (int)sum_ldk, pbytes);
     if (by_args) {
-        if ((e = launch_upload(hp, pbytes, dp, stream)) != hipSuccess) return hip_fail(e, "query: upload parameters");
+        if (!narrow && (e = launch_upload(hp, pbytes, dp, stream)) != hipSuccess)
+            return hip_fail(e, "query: upload parameters");
     } else {
         if ((e = hipMemcpyAsync(dp, hp, pbytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
             return hip_fail(e, "query: upload parameters");
@@ -471,8 +461,9 @@ int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wm
         (void)hipEventRecord(c->ev[slot][0], stream);
     }
     const int32_t* dqg = reinterpret_cast<const int32_t*>(dp + off_qg);
-    if ((e = launch_dist(dc, dq, dqg, G, opt.precision == WMD_DIST_BF16, stream)) != hipSuccess)
-        return hip_fail(e, "query: distance kernel launch");
+    if (narrow) e = launch_dist_narrow(dc, hq[0], dq, hp, pbytes, off_id, dp, bf16, stream);
+    else e = launch_dist(dc, dq, dqg, B, (int)sum_ldk, bf16, opt.log_domain, w.nrow, stream);
+    if (e != hipSuccess) return hip_fail(e, "query: distance kernel launch");
     ++launches;
     if (slot >= 0) (void)hipEventRecord(c->ev[slot][1], stream);
 

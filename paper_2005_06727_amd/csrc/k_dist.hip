@@ -2,27 +2,27 @@
 // Algorithm 1's first step, restricted to the query rows, Sec. 4; done as a
 // matrix product as Sec. 6 proposes, here on the CDNA4 matrix cores).
 //
-// For a group of queries (blockIdx.y) and a tile of corpus words i (blockIdx.x):
-//   G[i, k]  = <E[word(i)], E[qid[k]]>                 MFMA, FP32 or BF16 operands
-//   d2       = |E[word(i)]|^2 + |E[qid[k]]|^2 - 2 G     (FP32)
-//   d        = 0 when word(i) == qid[k];
-//              sqrt(sum_d (E[word(i), d] - E[qid[k], d])^2) in FP32 when d2 < tau^2
+// The query words of every query of a call form the columns of one GEMM
+// (query b owns global columns [kofs[b], kofs[b] + ldk_b)).  For a tile of 64
+// corpus words i and TC columns c (query b, local column k):
+//   G[i, c]  = <E[word(i)], E[qid_b[k]]>               MFMA, FP32 or BF16 operands
+//   d2       = |E[word(i)]|^2 + |E[qid_b[k]]|^2 - 2 G   (FP32, norms of the operand values)
+//   d        = 0 when word(i) == qid_b[k];
+//              sqrt(sum_d (E[word(i), d] - E[qid_b[k], d])^2) in FP32 when d2 < tau^2
 //              (the expansion cancels there); sqrt(max(d2, 0)) otherwise
-//   n_i      = min_k d[i, k] over the query's words when the log-domain shift
-//              is on, else 0
-//   Kt[i, k] = exp(-lambda (d - n_i)),  KMt[i, k] = Kt[i, k] * d
-// Columns m <= k < ldk are written as zeros.
+//   Kt_b[i, k] = exp(-lambda d), KMt_b[i, k] = Kt_b[i, k] * d (small lambda only);
+//   with the log-domain shift the tile writes d and folds it into
+//   n_i = min_k d[i, k] (an atomic minimum), and k_shift_exp then writes
+//   Kt_b[i, k] = exp(-lambda (d - n_i)).
+// Columns m_b <= k < ldk_b are written as zeros.
 //
-// Split-K: the 4 waves of a block share the tile's corpus rows and each takes
-// a slice of the embedding dimension (FP32: 32 rows, 4 slices; BF16: 2 x 32
-// rows, 2 slices); each wave computes two 16-row groups so that every query
-// fragment it loads serves 32 corpus rows.  A wave loads its slice of the corpus rows into
-// registers once (every load in flight together) and keeps it for every query
-// column chunk of the group; the query fragments come straight from global
-// memory (they are few and cache-resident).  The slices' partial products are
-// summed through LDS in a fixed order, so results do not depend on timing.
+// Each block streams its 64 corpus rows through LDS in chunks of the embedding
+// dimension (128 or 256 bytes per row and chunk), double buffered: the global loads
+// of chunk c + 1 are in flight while the matrix cores work on chunk c.  The
+// query columns are staged the same way.  Tiles are ordered so that the
+// column tiles of one row tile run on the same XCD and share its L2.
 #include <algorithm>
-#include <type_traits>
+#include <cstring>
 
 #include "wmd_internal.h"
 
@@ -33,35 +33,22 @@ namespace {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
-constexpr int BN = 32;     // query columns per chunk (2 MFMA column blocks)
-constexpr int KB = 64;     // embedding elements per fragment step of the whole block
-constexpr int NFMAX = 16;  // fragments per wave per register-resident chunk (ldv <= 1024)
-
-template <bool BF16> struct Op;
-template <> struct Op<false> {   // v_mfma_f32_16x16x4_f32: float4 fragment = 4 MFMAs, 16 k
-    typedef float4 Frag;
-    static constexpr int RGW = 1;   // waves along rows per block
-    static constexpr int KSPL = 4;  // k slices per block
-    static constexpr int KF = 16;   // k per fragment (4 lane groups x 4)
-};
-template <> struct Op<true> {    // v_mfma_f32_16x16x32_bf16: 8 bf16 per lane, 32 k
-    typedef uint4 Frag;
-    static constexpr int RGW = 2;
-    static constexpr int KSPL = 2;
-    static constexpr int KF = 32;
-};
-constexpr int RT = 2;   // 16-row groups per wave: each query fragment load serves 32 corpus rows
+constexpr int TR = 64;        // corpus rows per tile
 
 struct DistArgs {
-    const float* act;        // U x ldv FP32
-    const uint16_t* act16;   // U x ldv BF16 (BF16 path)
-    const float* norm;       // U: |row|^2 matching the operand precision
-    const int32_t* act_word; // U
-    const float* vecs;       // V x ldv FP32 (query rows)
-    const QueryDev* qd;
-    const int32_t* qgroup;   // G+1: queries [qgroup[g], qgroup[g+1]) form group g
+    const float* act;         // U x ldv FP32
+    const uint16_t* act16;    // U x ldv BF16 (BF16 path)
+    const float* norm;        // U: |row|^2 matching the operand precision
+    const int32_t* act_word;  // U
+    const float* vecs;        // V x ldv FP32 (query rows)
+    const QueryDev* qd;       // B queries
+    const int32_t* kofs;      // B + 1: first global column of each query
     int64_t U;
     int32_t ldv;
+    int32_t B;
+    int32_t ncols;            // kofs[B]
+    int32_t tiles_c;
+    int32_t nblocks;
 };
 
 __device__ __forceinline__ uint16_t bf16_rne(float f) {
@@ -89,21 +76,6 @@ __device__ float direct_d2(const float* __restrict__ a, const float* __restrict_
     return s;
 }
 
-template <int CTRL>
-__device__ __forceinline__ float dppf(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-
-// min over 32 consecutive lanes
-__device__ __forceinline__ float min32(float v) {
-    v = fminf(v, dppf<0xB1>(v));     // lane ^ 1
-    v = fminf(v, dppf<0x4E>(v));     // lane ^ 2
-    v = fminf(v, dppf<0x141>(v));    // other quad of the 8 (quads uniform)
-    v = fminf(v, dppf<0x140>(v));    // other half of the row (halves uniform)
-    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-    return fminf(__uint_as_float(r[0]), __uint_as_float(r[1]));   // rows 2j, 2j+1
-}
-
 // sum over the 4 lane groups (lanes l, l^16, l^32, l^48)
 __device__ __forceinline__ float sum_lane_groups(float v) {
     auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
@@ -112,257 +84,465 @@ __device__ __forceinline__ float sum_lane_groups(float v) {
     return __uint_as_float(t[0]) + __uint_as_float(t[1]);
 }
 
-// NF: fragments per wave per chunk; one chunk covers KSPL*NF*KF embedding
-// elements (the launcher picks NF = ldv / 64 when ldv <= 1024).
-template <bool BF16, int NF>
-__global__ __launch_bounds__(256) void k_dist(DistArgs a) {
-    typedef Op<BF16> O;
-    typedef typename O::Frag Frag;
-    constexpr int RGW = O::RGW, KSPL = O::KSPL, KF = O::KF;
-    constexpr int TR = 16 * RT * RGW;        // rows per tile
-    constexpr int KCH = KSPL * NF * KF;      // embedding elements per chunk
-    __shared__ float red[KSPL][TR][BN + 1];  // partial products of the k slices
-    __shared__ float qnp[KSPL][BN];          // partial query norms
-    __shared__ int32_t s_qid[BN];
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int rw = wave / KSPL, ks = wave % KSPL;   // row wave, k slice of this wave
-    const int lr = lane & 15;                       // operand row / result column
-    const int lg = lane >> 4;                       // lane group
-    const int64_t row0 = (int64_t)blockIdx.x * TR;
-    // row group t of this wave: rows row0 + (rw * RT + t) * 16 + 0..15
-    const int ldv = a.ldv;
-    const int nkc = (ldv + KCH - 1) / KCH;
-    const int q_begin = a.qgroup[blockIdx.y], q_end = a.qgroup[blockIdx.y + 1];
-
-    // fragment f of this wave covers k = kc*KCH + (ks*NF + f)*KF + lg*(KF/4) .. + KF/4 - 1
-    auto kof = [&](int kc, int f) { return kc * KCH + (ks * NF + f) * KF + lg * (KF / 4); };
-    // epilogue ownership: thread t handles (row t/32 + 8j, column t%32), j < TR/8;
-    // its rows' vocabulary ids and norms are fetched before the operand stream
-    constexpr int EJ = TR / 8;
-    const int ec = tid & 31, er = tid >> 5;
-    int e_word[EJ];
-    float e_norm[EJ];
-#pragma unroll
-    for (int j = 0; j < EJ; ++j) {
-        const int64_t gi = row0 + er + 8 * j;
-        e_word[j] = (gi < a.U) ? a.act_word[gi] : -2;
-        e_norm[j] = (gi < a.U) ? a.norm[gi] : 0.f;
+// query of a global column: the largest b with kofs[b] <= c
+__device__ __forceinline__ int query_of(const int32_t* kofs, int B, int c) {
+    int lo = 0, hi = B - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (kofs[mid] <= c) lo = mid;
+        else hi = mid - 1;
     }
+    return lo;
+}
 
-    Frag A[RT][NF];
-    auto load_a = [&](int kc) {
+// Epilogue of a wave's sub-tile: lane (lr, lg) holds G[row 16 t + 4 lg + r]
+// [column 16 nb + lr] of the rows from rbase and columns from cbase.
+template <int RT>
+__device__ __forceinline__ void epilogue(const DistArgs& a, const v4f (&acc)[RT][2], const float (&qn)[2],
+                                         const int (&e_word)[RT][4], const float (&e_norm)[RT][4],
+                                         const int64_t rbase, const int cbase, const int lr, const int lg) {
+    const int ldv = a.ldv;
 #pragma unroll
-        for (int t = 0; t < RT; ++t) {
-            const int64_t arow = row0 + (rw * RT + t) * 16 + lr;
+    for (int nb = 0; nb < 2; ++nb) {
+        const float qnj = sum_lane_groups(qn[nb]);
+        const int c = cbase + 16 * nb + lr;
+        if (c >= a.ncols) continue;
+        const int b = query_of(a.kofs, a.B, c);
+        const int k = c - a.kofs[b];
+        const QueryDev* q = a.qd + b;
+        const int m = q->m, ldk = q->ldk;
+        const int qw = (k < m) ? q->qid[k] : -1;
+        const float lam = q->lambda, tau2 = q->tau2;
+        const bool shift = q->shift != 0, km = !q->km_from_k;
 #pragma unroll
-            for (int f = 0; f < NF; ++f) {
-                const int k = kof(kc, f);
-                Frag z;
-                if constexpr (BF16) z = make_uint4(0u, 0u, 0u, 0u);
-                else z = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (arow < a.U && k < ldv) {
-                    if constexpr (BF16) z = *reinterpret_cast<const uint4*>(a.act16 + arow * ldv + k);
-                    else z = *reinterpret_cast<const float4*>(a.act + arow * ldv + k);
-                }
-                A[t][f] = z;
-            }
-        }
-    };
-    bool a_loaded = false;   // one chunk: A is loaded once, after the first query fragments
-
-    for (int qi = q_begin; qi < q_end; ++qi) {
-        const QueryDev q = a.qd[qi];
-        const int m = q.m, ldk = q.ldk;
-        const float lam = q.lambda;
-        float rmin[EJ];
+        for (int t = 0; t < RT; ++t)
 #pragma unroll
-        for (int j = 0; j < EJ; ++j) rmin[j] = INFINITY;
-
-        for (int col0 = 0; col0 < ldk; col0 += BN) {
-            const int nb_act = min(2, (ldk - col0 + 15) / 16);
-            int w[2];
-#pragma unroll
-            for (int nb = 0; nb < 2; ++nb) {
-                const int c = col0 + nb * 16 + lr;
-                w[nb] = (c < m) ? q.qid[c] : -1;
-            }
-            v4f acc[RT][2];
-#pragma unroll
-            for (int t = 0; t < RT; ++t) acc[t][0] = acc[t][1] = v4f{0.f, 0.f, 0.f, 0.f};
-            float qn[2] = {0.f, 0.f};
-            for (int kc = 0; kc < nkc; ++kc) {
-                // query fragments of this wave's slice for both column blocks (issued
-                // before the corpus rows so the MFMAs can start while those stream in)
-                Frag B[2][NF];
-#pragma unroll
-                for (int nb = 0; nb < 2; ++nb) {
-#pragma unroll
-                    for (int f = 0; f < NF; ++f) {
-                        const int k = kof(kc, f);
-                        Frag z;
-                        if constexpr (BF16) z = make_uint4(0u, 0u, 0u, 0u);
-                        else z = make_float4(0.f, 0.f, 0.f, 0.f);
-                        if (nb < nb_act && w[nb] >= 0 && k < ldv) {
-                            const float* src = a.vecs + (int64_t)w[nb] * ldv + k;
-                            if constexpr (!BF16) {
-                                z = *reinterpret_cast<const float4*>(src);
-                            } else {
-                                const float4 f0 = reinterpret_cast<const float4*>(src)[0];
-                                const float4 f1 = reinterpret_cast<const float4*>(src)[1];
-                                z.x = bf16_rne(f0.x) | ((uint32_t)bf16_rne(f0.y) << 16);
-                                z.y = bf16_rne(f0.z) | ((uint32_t)bf16_rne(f0.w) << 16);
-                                z.z = bf16_rne(f1.x) | ((uint32_t)bf16_rne(f1.y) << 16);
-                                z.w = bf16_rne(f1.z) | ((uint32_t)bf16_rne(f1.w) << 16);
-                            }
-                        }
-                        B[nb][f] = z;
-                    }
-                }
-                if (nkc > 1) {
-                    load_a(kc);
-                } else if (!a_loaded) {
-                    load_a(0);
-                    a_loaded = true;
-                }
-                // |q|^2 of the operand values (partial over this lane's k)
-#pragma unroll
-                for (int nb = 0; nb < 2; ++nb) {
-#pragma unroll
-                    for (int f = 0; f < NF; ++f) {
-                        if constexpr (!BF16) {
-                            const float4 b = B[nb][f];
-                            qn[nb] = fmaf(b.x, b.x, qn[nb]);
-                            qn[nb] = fmaf(b.y, b.y, qn[nb]);
-                            qn[nb] = fmaf(b.z, b.z, qn[nb]);
-                            qn[nb] = fmaf(b.w, b.w, qn[nb]);
-                        } else {
-                            const uint4 b = B[nb][f];
-                            const uint32_t ws[4] = {b.x, b.y, b.z, b.w};
-#pragma unroll
-                            for (int e = 0; e < 4; ++e) {
-                                const float lo = bf16_lo(ws[e]), hi = bf16_hi(ws[e]);
-                                qn[nb] = fmaf(lo, lo, qn[nb]);
-                                qn[nb] = fmaf(hi, hi, qn[nb]);
-                            }
-                        }
-                    }
-                }
-                auto mma = [&](auto nbc) {
-                    constexpr int NB = decltype(nbc)::value;
-#pragma unroll
-                    for (int f = 0; f < NF; ++f) {
-#pragma unroll
-                        for (int t = 0; t < RT; ++t) {
-#pragma unroll
-                            for (int nb = 0; nb < NB; ++nb) {
-                                v4f& c = acc[t][nb];
-                                if constexpr (!BF16) {
-                                    const float4 av = A[t][f], bv = B[nb][f];
-                                    c = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, c, 0, 0, 0);
-                                    c = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.y, c, 0, 0, 0);
-                                    c = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bv.z, c, 0, 0, 0);
-                                    c = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv.w, c, 0, 0, 0);
-                                } else {
-                                    const uint4 ai = A[t][f], bi = B[nb][f];
-                                    const v8bf av = *reinterpret_cast<const v8bf*>(&ai);
-                                    const v8bf bv = *reinterpret_cast<const v8bf*>(&bi);
-                                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
-                                }
-                            }
-                        }
-                    }
-                };
-                if (nb_act == 2) mma(std::integral_constant<int, 2>());
-                else mma(std::integral_constant<int, 1>());
-            }
-            // partial results of this slice -> LDS: lane holds G[4*lg + r][16*nb + lr]
-#pragma unroll
-            for (int nb = 0; nb < 2; ++nb) {
-#pragma unroll
-                for (int t = 0; t < RT; ++t)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        red[ks][(rw * RT + t) * 16 + 4 * lg + r][nb * 16 + lr] = acc[t][nb][r];
-                const float qs = sum_lane_groups(qn[nb]);
-                if (rw == 0 && lg == 0) qnp[ks][nb * 16 + lr] = qs;
-            }
-            if (tid < BN) s_qid[tid] = (col0 + tid < m) ? q.qid[col0 + tid] : -1;
-            __syncthreads();
-
-            // epilogue: sum the slices in order, then distance, K and K .* M
-            const int gj = col0 + ec;
-            const int qw = s_qid[ec];
-            float qnj = 0.f;
-#pragma unroll
-            for (int s2 = 0; s2 < KSPL; ++s2) qnj += qnp[s2][ec];
-#pragma unroll
-            for (int j = 0; j < EJ; ++j) {
-                const int rr = er + 8 * j;
-                const int64_t gi = row0 + rr;
-                if (gi >= a.U || gj >= ldk) continue;
-                float* kt = q.Kt + gi * ldk + gj;
-                float* km = q.KMt + gi * ldk + gj;
-                if (gj >= m) {
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gi = rbase + 16 * t + 4 * lg + r;
+                if (gi >= a.U) continue;
+                float* kt = q->Kt + gi * ldk + k;
+                if (k >= m) {
                     *kt = 0.f;
-                    if (!q.km_from_k) *km = 0.f;
+                    if (km) q->KMt[gi * ldk + k] = 0.f;
                     continue;
                 }
-                float g = 0.f;
-#pragma unroll
-                for (int s2 = 0; s2 < KSPL; ++s2) g += red[s2][rr][ec];
                 float d;
-                if (e_word[j] == qw) {
+                if (e_word[t][r] == qw) {
                     d = 0.f;
                 } else {
-                    float d2 = e_norm[j] + qnj - 2.f * g;
-                    if (d2 < q.tau2) d2 = direct_d2(a.act + gi * ldv, a.vecs + (int64_t)qw * ldv, ldv);
+                    float d2 = e_norm[t][r] + qnj - 2.f * acc[t][nb][r];
+                    if (d2 < tau2) d2 = direct_d2(a.act + gi * ldv, a.vecs + (int64_t)qw * ldv, ldv);
                     d = sqrtf(fmaxf(d2, 0.f));
                 }
-                if (q.shift) {
+                if (shift) {
                     *kt = d;
-                    rmin[j] = fminf(rmin[j], d);
+                    // d >= 0, so the bit patterns order like the values
+                    atomicMin(reinterpret_cast<unsigned int*>(q->nrow + gi), __float_as_uint(d));
                 } else {
                     const float kv = expf(-lam * d);
                     *kt = kv;
-                    if (!q.km_from_k) *km = kv * d;
+                    if (km) q->KMt[gi * ldk + k] = kv * d;
                 }
             }
-            __syncthreads();   // red, qnp, s_qid are reused by the next chunk
+    }
+}
+
+// TC: query columns per tile (32: 4 waves of 16 rows x 32 columns; 64: 2 x 2
+// waves of 32 x 32).  CHB: bytes per row and chunk; the narrow tile (one short
+// query, bound by HBM) streams bigger chunks to keep more bytes in flight.
+template <bool BF16, int TC, int CHB>
+__global__ __launch_bounds__(256) void k_dist(DistArgs a) {
+    constexpr int SB = CHB + 16;                // LDS row stride: 8 lanes on distinct banks
+    constexpr int RT = (TC == 64) ? 2 : 1;      // 16-row groups per wave
+    constexpr int NB = 2;                       // 16-column groups per wave
+    constexpr int AP = TR * (CHB / 16) / 256;   // A staging pieces per thread
+    constexpr int BP = TC * (CHB / 16) / 256;   // B staging pieces per thread
+    constexpr int SEG = CHB / 16;               // 16-byte segments per row and chunk
+    constexpr int KS = CHB / 128;               // 128-byte sub-chunks per chunk
+    __shared__ __attribute__((aligned(16))) char As[2][TR * SB];
+    __shared__ __attribute__((aligned(16))) char Bs[2][TC * SB];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+    const int wr = (TC == 64) ? (wave >> 1) : wave;
+    const int wc = (TC == 64) ? (wave & 1) : 0;
+
+    // XCD-aware tile order: blocks b and b + 8 share an XCD, so consecutive
+    // logical tiles (the column tiles of one row tile) go to the same XCD
+    int L = blockIdx.x;
+    const int nb8 = a.nblocks / 8 * 8;
+    if (L < nb8) L = (L % 8) * (a.nblocks / 8) + L / 8;
+    const int64_t row0 = (int64_t)(L / a.tiles_c) * TR;
+    const int col0 = (L % a.tiles_c) * TC;
+    const int ldv = a.ldv;
+    const int nchunks = ldv * (BF16 ? 2 : 4) / CHB;
+
+    // ---- staging sources: A pieces (row, 16-byte segment), B pieces (column, segment)
+    const char* asrc[AP];
+#pragma unroll
+    for (int j = 0; j < AP; ++j) {
+        const int p = tid + 256 * j;
+        const int64_t row = row0 + p / SEG;
+        asrc[j] = nullptr;
+        if (row < a.U) {
+            if constexpr (BF16) asrc[j] = reinterpret_cast<const char*>(a.act16 + row * ldv) + (p % SEG) * 16;
+            else asrc[j] = reinterpret_cast<const char*>(a.act + row * ldv) + (p % SEG) * 16;
+        }
+    }
+    const float* bsrc[BP];
+#pragma unroll
+    for (int j = 0; j < BP; ++j) {
+        const int p = tid + 256 * j;
+        const int c = col0 + p / SEG;
+        bsrc[j] = nullptr;
+        if (c < a.ncols) {
+            const int b = query_of(a.kofs, a.B, c);
+            const int k = c - a.kofs[b];
+            const QueryDev* q = a.qd + b;
+            // FP32: 4 floats per segment; BF16: 8 floats rounded to 8 bf16
+            if (k < q->m) bsrc[j] = a.vecs + (int64_t)q->qid[k] * ldv + (p % SEG) * (BF16 ? 8 : 4);
+        }
+    }
+    uint4 ra[AP], rb[BP];
+    auto load_chunk = [&](int ch) {
+#pragma unroll
+        for (int j = 0; j < AP; ++j)
+            ra[j] = asrc[j] ? *reinterpret_cast<const uint4*>(asrc[j] + ch * CHB) : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+        for (int j = 0; j < BP; ++j) {
+            if constexpr (BF16) {
+                if (bsrc[j]) {
+                    const float4 f0 = reinterpret_cast<const float4*>(bsrc[j] + ch * (CHB / 2))[0];
+                    const float4 f1 = reinterpret_cast<const float4*>(bsrc[j] + ch * (CHB / 2))[1];
+                    rb[j].x = bf16_rne(f0.x) | ((uint32_t)bf16_rne(f0.y) << 16);
+                    rb[j].y = bf16_rne(f0.z) | ((uint32_t)bf16_rne(f0.w) << 16);
+                    rb[j].z = bf16_rne(f1.x) | ((uint32_t)bf16_rne(f1.y) << 16);
+                    rb[j].w = bf16_rne(f1.z) | ((uint32_t)bf16_rne(f1.w) << 16);
+                } else {
+                    rb[j] = make_uint4(0u, 0u, 0u, 0u);
+                }
+            } else {
+                rb[j] = bsrc[j] ? *reinterpret_cast<const uint4*>(bsrc[j] + ch * (CHB / 4)) : make_uint4(0u, 0u, 0u, 0u);
+            }
+        }
+    };
+    auto store_chunk = [&](int buf) {
+#pragma unroll
+        for (int j = 0; j < AP; ++j) {
+            const int p = tid + 256 * j;
+            *reinterpret_cast<uint4*>(&As[buf][(p / SEG) * SB + (p % SEG) * 16]) = ra[j];
+        }
+#pragma unroll
+        for (int j = 0; j < BP; ++j) {
+            const int p = tid + 256 * j;
+            *reinterpret_cast<uint4*>(&Bs[buf][(p / SEG) * SB + (p % SEG) * 16]) = rb[j];
+        }
+    };
+
+    // ---- epilogue metadata, fetched before the operand stream
+    int e_word[RT][4];
+    float e_norm[RT][4];
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t gi = row0 + wr * 16 * RT + 16 * t + 4 * lg + r;
+            e_word[t][r] = (gi < a.U) ? a.act_word[gi] : -2;
+            e_norm[t][r] = (gi < a.U) ? a.norm[gi] : 0.f;
         }
 
-        if (q.shift) {
-            // n_i = min_k d[i, k]: this thread's columns (done), then the 32 threads of the row
+    load_chunk(0);
+    store_chunk(0);
+    __syncthreads();
+
+    v4f acc[RT][NB];
 #pragma unroll
-            for (int j = 0; j < EJ; ++j) {
-                rmin[j] = min32(rmin[j]);
-                const int64_t gi = row0 + er + 8 * j;
-                if (ec == 0 && gi < a.U) q.nrow[gi] = rmin[j];
-            }
-            for (int col0 = 0; col0 < ldk; col0 += BN) {
-                const int gj = col0 + ec;
+    for (int t = 0; t < RT; ++t)
 #pragma unroll
-                for (int j = 0; j < EJ; ++j) {
-                    const int64_t gi = row0 + er + 8 * j;
-                    if (gi >= a.U || gj >= m) continue;
-                    float* kt = q.Kt + gi * ldk + gj;
-                    const float d = *kt;                   // written by this same thread above
-                    const float kv = expf(-lam * (d - rmin[j]));
-                    *kt = kv;
-                    if (!q.km_from_k) q.KMt[gi * ldk + gj] = kv * d;
+        for (int nb = 0; nb < NB; ++nb) acc[t][nb] = v4f{0.f, 0.f, 0.f, 0.f};
+    float qn[NB] = {0.f, 0.f};
+
+    for (int ch = 0; ch < nchunks; ++ch) {
+        const int buf = ch & 1;
+        if (ch + 1 < nchunks) load_chunk(ch + 1);
+        // lane (lr, lg) takes bytes [32 lg, 32 lg + 32) of every 128-byte piece of
+        // a row, in the same order as k_dist_narrow (results do not depend on
+        // which kernel ran)
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            uint4 fa[RT][2], fb[NB][2];
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                    fa[t][h] = *reinterpret_cast<const uint4*>(
+                        &As[buf][(wr * 16 * RT + 16 * t + lr) * SB + ks * 128 + lg * 32 + 16 * h]);
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                    fb[nb][h] = *reinterpret_cast<const uint4*>(
+                        &Bs[buf][(wc * 32 + 16 * nb + lr) * SB + ks * 128 + lg * 32 + 16 * h]);
+            // |q|^2 of the operand values (partial over this lane's k)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const uint32_t w4[4] = {fb[nb][h].x, fb[nb][h].y, fb[nb][h].z, fb[nb][h].w};
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        if constexpr (BF16) {
+                            const float lo = bf16_lo(w4[e]), hi = bf16_hi(w4[e]);
+                            qn[nb] = fmaf(lo, lo, qn[nb]);
+                            qn[nb] = fmaf(hi, hi, qn[nb]);
+                        } else {
+                            const float f = __uint_as_float(w4[e]);
+                            qn[nb] = fmaf(f, f, qn[nb]);
+                        }
+                    }
                 }
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int t = 0; t < RT; ++t)
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) {
+                        v4f& c = acc[t][nb];
+                        const uint4 av = fa[t][h], bv = fb[nb][h];
+                        if constexpr (BF16) {
+                            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const v8bf*>(&av),
+                                                                        *reinterpret_cast<const v8bf*>(&bv), c, 0, 0, 0);
+                        } else {
+                            c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av.x), __uint_as_float(bv.x), c, 0, 0, 0);
+                            c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av.y), __uint_as_float(bv.y), c, 0, 0, 0);
+                            c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av.z), __uint_as_float(bv.z), c, 0, 0, 0);
+                            c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av.w), __uint_as_float(bv.w), c, 0, 0, 0);
+                        }
+                    }
+        }
+        if (ch + 1 < nchunks) store_chunk(buf ^ 1);
+        __syncthreads();
+    }
+
+    epilogue<RT>(a, acc, qn, e_word, e_norm, row0 + wr * 16 * RT, col0 + wc * 32, lr, lg);
+}
+
+// One short query (at most 32 columns), bound by reading the corpus rows.
+// The query travels in the kernel arguments (its fields, and the whole
+// parameter block, which block 0 stores to device memory for the Sinkhorn
+// kernel), so no upload launch and no dependent metadata loads precede the
+// stream.  The block first stages the query columns in LDS, then each wave
+// issues the loads of its 16 corpus rows (the whole embedding dimension) into
+// registers at once and the MFMAs consume them as they arrive.  Lane (lr, lg)
+// loads row lr, bytes [128 c + 32 lg, +32) of every 128-byte chunk c, so four
+// lanes read one full cache line; the general kernel uses the same k order,
+// so results do not depend on which kernel ran.
+struct NarrowArgs {
+    const float* act;
+    const uint16_t* act16;
+    const float* norm;
+    const int32_t* act_word;
+    const float* vecs;
+    int64_t U;
+    int32_t ldv;
+    float* Kt;
+    float* KMt;
+    float* nrow;
+    float lambda, tau2;
+    int32_t m, ldk, shift, km;   // km: K1 also writes KMt
+    int32_t qid_word;            // word index of the query ids in blob
+    int32_t pwords;              // parameter block words
+    uint32_t* params;            // device parameter block
+    uint32_t blob[kUploadChunkBytes / 4];
+};
+
+template <bool BF16, int NC>
+__global__ __launch_bounds__(256) void k_dist_narrow(NarrowArgs a) {
+    constexpr int SBB = NC * 128 + 16;   // LDS column stride (bytes): 8 lanes on distinct banks
+    __shared__ __attribute__((aligned(16))) char Bs[32 * SBB];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+    const int64_t rbase = (int64_t)blockIdx.x * TR + 16 * wave;
+    const int ldv = a.ldv, m = a.m;
+
+    if (blockIdx.x == 0)
+        for (int i = tid; i < a.pwords; i += 256) a.params[i] = a.blob[i];
+
+    // query columns -> LDS: 16-byte pieces, 32 columns x 8 NC pieces, NC per thread
+    {
+        uint4 v[NC];
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            const int p = tid + 256 * j;
+            const int cl = p / (8 * NC), seg = p % (8 * NC);
+            v[j] = make_uint4(0u, 0u, 0u, 0u);
+            if (cl < m) {
+                const float* src = a.vecs + (int64_t)(int32_t)a.blob[a.qid_word + cl] * ldv;
+                if constexpr (BF16) {
+                    const float4 f0 = reinterpret_cast<const float4*>(src + seg * 8)[0];
+                    const float4 f1 = reinterpret_cast<const float4*>(src + seg * 8)[1];
+                    v[j].x = bf16_rne(f0.x) | ((uint32_t)bf16_rne(f0.y) << 16);
+                    v[j].y = bf16_rne(f0.z) | ((uint32_t)bf16_rne(f0.w) << 16);
+                    v[j].z = bf16_rne(f1.x) | ((uint32_t)bf16_rne(f1.y) << 16);
+                    v[j].w = bf16_rne(f1.z) | ((uint32_t)bf16_rne(f1.w) << 16);
+                } else {
+                    v[j] = *reinterpret_cast<const uint4*>(src + seg * 4);
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            const int p = tid + 256 * j;
+            *reinterpret_cast<uint4*>(&Bs[(p / (8 * NC)) * SBB + (p % (8 * NC)) * 16]) = v[j];
+        }
+    }
+    uint4 fa[NC][2];
+    {
+        const int64_t row = rbase + lr;
+        if (row < a.U) {
+            const char* src = BF16 ? reinterpret_cast<const char*>(a.act16 + row * ldv)
+                                   : reinterpret_cast<const char*>(a.act + row * ldv);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                fa[c][0] = *reinterpret_cast<const uint4*>(src + c * 128 + lg * 32);
+                fa[c][1] = *reinterpret_cast<const uint4*>(src + c * 128 + lg * 32 + 16);
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) fa[c][0] = fa[c][1] = make_uint4(0u, 0u, 0u, 0u);
+        }
+    }
+    int e_word[4];
+    float e_norm[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t gi = rbase + 4 * lg + r;
+        e_word[r] = (gi < a.U) ? a.act_word[gi] : -2;
+        e_norm[r] = (gi < a.U) ? a.norm[gi] : 0.f;
+    }
+    int qw[2];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+        const int k = 16 * nb + lr;
+        qw[nb] = (k < m) ? (int32_t)a.blob[a.qid_word + k] : -1;
+    }
+    __syncthreads();
+
+    v4f acc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
+    float qn[2] = {0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        uint4 fb[2][2];
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                fb[nb][h] = *reinterpret_cast<const uint4*>(&Bs[(16 * nb + lr) * SBB + c * 128 + lg * 32 + 16 * h]);
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const uint32_t w4[4] = {fb[nb][h].x, fb[nb][h].y, fb[nb][h].z, fb[nb][h].w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if constexpr (BF16) {
+                        const float lo = bf16_lo(w4[e]), hi = bf16_hi(w4[e]);
+                        qn[nb] = fmaf(lo, lo, qn[nb]);
+                        qn[nb] = fmaf(hi, hi, qn[nb]);
+                    } else {
+                        const float f = __uint_as_float(w4[e]);
+                        qn[nb] = fmaf(f, f, qn[nb]);
+                    }
+                }
+            }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+                v4f& cc = acc[nb];
+                const uint4 av = fa[c][h], bv = fb[nb][h];
+                if constexpr (BF16) {
+                    cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const v8bf*>(&av),
+                                                                 *reinterpret_cast<const v8bf*>(&bv), cc, 0, 0, 0);
+                } else {
+                    cc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av.x), __uint_as_float(bv.x), cc, 0, 0, 0);
+                    cc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av.y), __uint_as_float(bv.y), cc, 0, 0, 0);
+                    cc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av.z), __uint_as_float(bv.z), cc, 0, 0, 0);
+                    cc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av.w), __uint_as_float(bv.w), cc, 0, 0, 0);
+                }
+            }
+    }
+
+    // epilogue (the same arithmetic as the general kernel's)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+        const float qnj = sum_lane_groups(qn[nb]);
+        const int k = 16 * nb + lr;
+        if (k >= a.ldk) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t gi = rbase + 4 * lg + r;
+            if (gi >= a.U) continue;
+            float* kt = a.Kt + gi * a.ldk + k;
+            if (k >= m) {
+                *kt = 0.f;
+                if (a.km) a.KMt[gi * a.ldk + k] = 0.f;
+                continue;
+            }
+            float d;
+            if (e_word[r] == qw[nb]) {
+                d = 0.f;
+            } else {
+                float d2 = e_norm[r] + qnj - 2.f * acc[nb][r];
+                if (d2 < a.tau2) d2 = direct_d2(a.act + gi * ldv, a.vecs + (int64_t)qw[nb] * ldv, ldv);
+                d = sqrtf(fmaxf(d2, 0.f));
+            }
+            if (a.shift) {
+                *kt = d;
+                atomicMin(reinterpret_cast<unsigned int*>(a.nrow + gi), __float_as_uint(d));
+            } else {
+                const float kv = expf(-a.lambda * d);
+                *kt = kv;
+                if (a.km) a.KMt[gi * a.ldk + k] = kv * d;
             }
         }
     }
 }
 
+// Log-domain shift, second pass: Kt holds d, nrow holds n_i = min_k d.
+__global__ __launch_bounds__(256) void k_shift_exp(const QueryDev* qd, int64_t U) {
+    const QueryDev q = qd[blockIdx.y];
+    const int64_t total = U * q.ldk;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int k = (int)(e % q.ldk);
+        if (k >= q.m) continue;
+        const int64_t i = e / q.ldk;
+        const float d = q.Kt[e];
+        const float kv = expf(-q.lambda * (d - q.nrow[i]));
+        q.Kt[e] = kv;
+        if (!q.km_from_k) q.KMt[e] = kv * d;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fill_inf(float* p, int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = INFINITY;
+}
+
 }  // namespace
 
-hipError_t launch_dist(const DevCorpus& c, const QueryDev* qd, const int32_t* qgroup, int groups, int bf16,
-                       hipStream_t s) {
-    if (groups <= 0 || c.U <= 0) return hipSuccess;
+hipError_t launch_dist(const DevCorpus& c, const QueryDev* qd, const int32_t* kofs, int B, int ncols, int bf16,
+                       int shift, float* nrow_all, hipStream_t s) {
+    if (B <= 0 || c.U <= 0 || ncols <= 0) return hipSuccess;
+    if (c.ldv % 64 != 0) return hipErrorInvalidValue;   // whole chunks
+    hipError_t e;
+    if (shift) {
+        const int64_t n = c.U * (int64_t)B;
+        hipLaunchKernelGGL(k_fill_inf, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0, s,
+                           nrow_all, n);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     DistArgs a;
     a.act = c.act;
     a.act16 = c.act_bf16;
@@ -370,26 +550,84 @@ hipError_t launch_dist(const DevCorpus& c, const QueryDev* qd, const int32_t* qg
     a.act_word = c.act_word;
     a.vecs = c.vecs;
     a.qd = qd;
-    a.qgroup = qgroup;
+    a.kofs = kofs;
     a.U = c.U;
     a.ldv = c.ldv;
-    const int tr = bf16 ? 64 : 32;   // 16 * RT * RGW
-    dim3 grid((unsigned)((c.U + tr - 1) / tr), (unsigned)groups);
-    // fragments per wave: ldv / 64 (one chunk) up to 1024 elements, chunks of 16 beyond
-    const int nf = std::min(NFMAX, (c.ldv + KB - 1) / KB);
-#define WMD_DIST_CASE(K)                                                              \
-    case K:                                                                           \
-        if (bf16) hipLaunchKernelGGL((k_dist<true, K>), grid, dim3(256), 0, s, a);    \
-        else hipLaunchKernelGGL((k_dist<false, K>), grid, dim3(256), 0, s, a);        \
+    a.B = B;
+    a.ncols = ncols;
+    const int tc = ncols <= 32 ? 32 : 64;
+    const int64_t tiles_r = (c.U + TR - 1) / TR;
+    a.tiles_c = (ncols + tc - 1) / tc;
+    const int64_t nblocks = tiles_r * a.tiles_c;
+    if (nblocks > INT32_MAX) return hipErrorInvalidValue;
+    a.nblocks = (int32_t)nblocks;
+    if (tc == 32) {
+        // FP32 rows are 4 * ldv bytes (a multiple of 256), BF16 rows 2 * ldv (of 128)
+        if (bf16) hipLaunchKernelGGL((k_dist<true, 32, 128>), dim3((unsigned)nblocks), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_dist<false, 32, 256>), dim3((unsigned)nblocks), dim3(256), 0, s, a);
+    } else {
+        if (bf16) hipLaunchKernelGGL((k_dist<true, 64, 128>), dim3((unsigned)nblocks), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_dist<false, 64, 128>), dim3((unsigned)nblocks), dim3(256), 0, s, a);
+    }
+    if ((e = hipGetLastError()) != hipSuccess || !shift) return e;
+    const int64_t per_q = (c.U * 64 + 255) / 256;
+    hipLaunchKernelGGL(k_shift_exp, dim3((unsigned)std::min<int64_t>(per_q, 2048), (unsigned)B), dim3(256), 0, s,
+                       qd, c.U);
+    return hipGetLastError();
+}
+
+bool dist_narrow_fits(const DevCorpus& c, int bf16, int B, int ncols, size_t pbytes) {
+    const int nc = c.ldv * (bf16 ? 2 : 4) / 128;
+    return B == 1 && ncols <= 32 && nc >= 1 && nc <= 12 && c.ldv % 64 == 0 && pbytes <= (size_t)kUploadChunkBytes &&
+           pbytes % 4 == 0 && (c.U + TR - 1) / TR <= INT32_MAX;
+}
+
+hipError_t launch_dist_narrow(const DevCorpus& c, const QueryDev& hq, const QueryDev* qd_dev, const void* blob,
+                              size_t pbytes, size_t off_id, void* params_dev, int bf16, hipStream_t s) {
+    NarrowArgs a;
+    a.act = c.act;
+    a.act16 = c.act_bf16;
+    a.norm = bf16 ? c.act_norm_bf16 : c.act_norm;
+    a.act_word = c.act_word;
+    a.vecs = c.vecs;
+    a.U = c.U;
+    a.ldv = c.ldv;
+    a.Kt = hq.Kt;
+    a.KMt = hq.KMt;
+    a.nrow = hq.nrow;
+    a.lambda = hq.lambda;
+    a.tau2 = hq.tau2;
+    a.m = hq.m;
+    a.ldk = hq.ldk;
+    a.shift = hq.shift;
+    a.km = hq.km_from_k ? 0 : 1;
+    a.qid_word = (int32_t)(off_id / 4);
+    a.pwords = (int32_t)(pbytes / 4);
+    a.params = static_cast<uint32_t*>(params_dev);
+    std::memset(a.blob, 0, sizeof a.blob);
+    std::memcpy(a.blob, blob, pbytes);
+    hipError_t e;
+    if (hq.shift) {
+        hipLaunchKernelGGL(k_fill_inf, dim3((unsigned)std::min<int64_t>((c.U + 255) / 256, 4096)), dim3(256), 0, s,
+                           hq.nrow, c.U);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    const int nc = c.ldv * (bf16 ? 2 : 4) / 128;
+    const unsigned blocks = (unsigned)((c.U + TR - 1) / TR);
+#define WMD_NARROW(K)                                                                           \
+    case K:                                                                                     \
+        if (bf16) hipLaunchKernelGGL((k_dist_narrow<true, K>), dim3(blocks), dim3(256), 0, s, a); \
+        else hipLaunchKernelGGL((k_dist_narrow<false, K>), dim3(blocks), dim3(256), 0, s, a);     \
         break;
-    switch (nf) {
-        WMD_DIST_CASE(1) WMD_DIST_CASE(2) WMD_DIST_CASE(3) WMD_DIST_CASE(4)
-        WMD_DIST_CASE(5) WMD_DIST_CASE(6) WMD_DIST_CASE(7) WMD_DIST_CASE(8)
-        WMD_DIST_CASE(9) WMD_DIST_CASE(10) WMD_DIST_CASE(11) WMD_DIST_CASE(12)
-        WMD_DIST_CASE(13) WMD_DIST_CASE(14) WMD_DIST_CASE(15) WMD_DIST_CASE(16)
+    switch (nc) {
+        WMD_NARROW(1) WMD_NARROW(2) WMD_NARROW(3) WMD_NARROW(4) WMD_NARROW(5) WMD_NARROW(6)
+        WMD_NARROW(7) WMD_NARROW(8) WMD_NARROW(9) WMD_NARROW(10) WMD_NARROW(11) WMD_NARROW(12)
         default: return hipErrorInvalidValue;
     }
-#undef WMD_DIST_CASE
+#undef WMD_NARROW
+    if ((e = hipGetLastError()) != hipSuccess || !hq.shift) return e;
+    hipLaunchKernelGGL(k_shift_exp, dim3((unsigned)std::min<int64_t>((c.U * 32 + 255) / 256, 2048), 1u), dim3(256),
+                       0, s, qd_dev, c.U);
     return hipGetLastError();
 }
 

@@ -48,7 +48,7 @@ struct Layout {
     size_t kfloats = 0, kmfloats = 0, xfloats = 0, nfloats = 0, pbytes = 0, obytes = 0;
     size_t sum_ldk = 0, sum_m = 0;
     size_t off_ql = 0, off_qg = 0, off_id = 0, off_r = 0, off_ri = 0;
-    int G = 1, max_m = 0, max_iters = 0, per_launch = 0;
+    int max_m = 0, max_iters = 0, per_launch = 0;
     bool chunked = false;
     size_t device_bytes() const;
 };

@@ -84,8 +84,17 @@ hipError_t launch_gather_rows(const float* vecs, const int32_t* ids, float* out,
 
 // Distance GEMM + epilogue: writes Kt / KMt of every query; the queries are
 // split into `groups` contiguous groups, qgroup[g] .. qgroup[g+1] (device).
-hipError_t launch_dist(const DevCorpus& c, const QueryDev* qd, const int32_t* qgroup, int groups, int bf16,
-                       hipStream_t s);
+// K1 over all queries of a call: kofs[B + 1] holds each query's first column
+// (prefix sums of ldk, kofs[B] = ncols).  With shift, nrow_all (U x B floats)
+// receives the row minima and a second pass turns Kt into exp(-lambda (d - n)).
+hipError_t launch_dist(const DevCorpus& c, const QueryDev* qd, const int32_t* kofs, int B, int ncols, int bf16,
+                       int shift, float* nrow_all, hipStream_t s);
+// K1 for one short query whose parameter block (at most kUploadChunkBytes, host
+// image with device pointers) travels as kernel arguments; block 0 stores it
+// at params_dev for the launches that follow.  hq: the query's fields.
+bool dist_narrow_fits(const DevCorpus& c, int bf16, int B, int ncols, size_t pbytes);
+hipError_t launch_dist_narrow(const DevCorpus& c, const QueryDev& hq, const QueryDev* qd_dev, const void* blob,
+                              size_t pbytes, size_t off_id, void* params_dev, int bf16, hipStream_t s);
 
 // Fused Sinkhorn iterations + final WMD step.  `shape` selects the register
 // tile (see k_sinkhorn.hip); shape < 0 selects the streaming kernel that
