@@ -196,6 +196,26 @@ int wmd_query_batch_async(wmd_corpus* corpus, int32_t B, const int64_t* q_ptr,
                           double* dev_resid, void* stream);
 
 /*
+ * Retrieval (the k nearest documents of a query, the use of WMD the paper
+ * motivates in Sec. 3): distances as wmd_query computes them, then the k
+ * smallest selected on the device.  Results ascend by (distance, document
+ * index): equal distances are ordered by the smaller index, so the answer is
+ * unique.  k in [1, min(N, WMD_MAX_TOPK)], else WMD_EINVAL; other errors as
+ * wmd_query.  out_idx receives k document indices (input order numbering),
+ * out_dist their k distances.
+ */
+#define WMD_MAX_TOPK 2048
+int wmd_query_topk(wmd_corpus* corpus, const int32_t* qids, const float* qweights,
+                   int32_t n, float lambda, int32_t iters, const wmd_query_options* opt,
+                   int32_t k, int32_t* out_idx, double* out_dist);
+
+/* Stream-ordered wmd_query_topk: dev_idx (k int32) and dev_dist (k doubles)
+ * are DEVICE pointers written in order on `stream`. */
+int wmd_query_topk_async(wmd_corpus* corpus, const int32_t* qids, const float* qweights,
+                         int32_t n, float lambda, int32_t iters, const wmd_query_options* opt,
+                         int32_t k, int32_t* dev_idx, double* dev_dist, void* stream);
+
+/*
  * Kernel timing, recorded with HIP events on the stream the kernels run on.
  * wmd_set_timing(corpus, k) with k > 0 clears the totals and records every
  * k-th query or batch call from then on (1: every call; event records cost

@@ -8,3 +8,4 @@ from .sinkhorn_wmd import (  # noqa: F401
     query_histogram, doc_histograms, dense_doc_matrix, word_distances,
     sinkhorn_wmd_dense, sinkhorn_wmd_sparse,
 )
+from .retrieval import knn  # noqa: F401

@@ -65,6 +65,9 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 }  // namespace
 
 void free_workspace(Workspace& w) {
+    dfree(w.tk);
+    hfree(w.tk_host);
+    w.tkcap = w.tkhcap = 0;
     if (!w.carved) {
         dfree(w.Kt);
         dfree(w.KMt);
@@ -821,6 +824,106 @@ int wmd_query_batch_async(wmd_corpus* c, int32_t B, const int64_t* q_ptr, const 
     if (!guard.ok()) return fail(WMD_EDEVICE, "batch: cannot select device");
     int slot = 0;
     return run_queries(c, qs, o, dev_dist, dev_resid, (hipStream_t)stream, false, &slot);
+}
+
+// Top-k of the distances in w.out: scratch and results in w.tk (grown when
+// needed, after the slot's previous work).  Leaves the results at w.tk and
+// re-records w.done after the selection.
+static int enqueue_topk(wmd_corpus* c, Workspace& w, int32_t k, hipStream_t stream, int32_t** res_idx,
+                        double** res_dist) {
+    const int64_t N = c->dc.N;
+    const size_t sb = align_up(topk_scratch_bytes(N, k), 256);
+    const size_t need = sb + align_up(sizeof(int32_t) * k, 256) + sizeof(double) * k;
+    hipError_t e;
+    if (need > w.tkcap) {
+        if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "top-k: wait");
+        dfree(w.tk);
+        w.tkcap = 0;
+        const size_t cap = need + need / 4;
+        if ((e = dalloc(&w.tk, cap)) != hipSuccess) return hip_fail(e, "top-k: scratch");
+        w.tkcap = cap;
+    }
+    *res_idx = reinterpret_cast<int32_t*>(w.tk + sb);
+    *res_dist = reinterpret_cast<double*>(w.tk + sb + align_up(sizeof(int32_t) * k, 256));
+    if ((e = launch_topk(w.out, N, k, w.tk, sb, *res_idx, *res_dist, stream)) != hipSuccess)
+        return hip_fail(e, "top-k: launch");
+    if ((e = hipEventRecord(w.done, stream)) != hipSuccess) return hip_fail(e, "top-k: record");
+    return WMD_OK;
+}
+
+static int check_topk(const wmd_corpus* c, int32_t k) {
+    if (k < 1 || (int64_t)k > c->dc.N || k > WMD_MAX_TOPK)
+        return fail(WMD_EINVAL, "top-k: k = %d outside [1, min(N, %d)]", k, WMD_MAX_TOPK);
+    return WMD_OK;
+}
+
+int wmd_query_topk(wmd_corpus* c, const int32_t* qids, const float* qweights, int32_t n, float lambda,
+                   int32_t iters, const wmd_query_options* opt, int32_t k, int32_t* out_idx, double* out_dist) {
+    if (!c || !out_idx || !out_dist) return fail(WMD_EINVAL, "top-k: null corpus or output");
+    int rc = check_topk(c, k);
+    if (rc) return rc;
+    wmd_query_options o;
+    if ((rc = wmd::check_query_options(opt, &o))) return rc;
+    std::vector<PlannedQuery> qs(1);
+    if ((rc = plan_query(c, qids, qweights, n, lambda, iters, o.precision == WMD_DIST_BF16, &qs[0]))) return rc;
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard guard(c->dc.device);
+    if (!guard.ok()) return fail(WMD_EDEVICE, "top-k: cannot select device");
+    double dummy = 0.0;
+    int slot = 0;
+    if ((rc = run_queries(c, qs, o, &dummy, nullptr, c->stream, true, &slot))) return rc;
+    Workspace& w = c->ws[slot];
+    int32_t* ri = nullptr;
+    double* rd = nullptr;
+    if ((rc = enqueue_topk(c, w, k, c->stream, &ri, &rd))) return rc;
+    hipError_t e;
+    const size_t hb = sizeof(double) * k + sizeof(int32_t) * k;
+    if (hb > w.tkhcap) {
+        if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(e, "top-k: wait");
+        hfree(w.tk_host);
+        w.tkhcap = 0;
+        if ((e = hipHostMalloc(reinterpret_cast<void**>(&w.tk_host), hb, hipHostMallocDefault)) != hipSuccess)
+            return hip_fail(e, "top-k: pinned results");
+        w.tkhcap = hb;
+    }
+    if ((e = hipMemcpyAsync(w.tk_host, rd, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(w.tk_host + sizeof(double) * k, ri, sizeof(int32_t) * k, hipMemcpyDeviceToHost,
+                            c->stream)) != hipSuccess)
+        return hip_fail(e, "top-k: download");
+    if ((e = hipEventRecord(w.done, c->stream)) != hipSuccess) return hip_fail(e, "top-k: record");
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(e, "top-k: execution");
+    std::memcpy(out_dist, w.tk_host, sizeof(double) * k);
+    std::memcpy(out_idx, w.tk_host + sizeof(double) * k, sizeof(int32_t) * k);
+    return WMD_OK;
+}
+
+int wmd_query_topk_async(wmd_corpus* c, const int32_t* qids, const float* qweights, int32_t n, float lambda,
+                         int32_t iters, const wmd_query_options* opt, int32_t k, int32_t* dev_idx, double* dev_dist,
+                         void* stream) {
+    if (!c || !dev_idx || !dev_dist) return fail(WMD_EINVAL, "top-k: null corpus or output");
+    int rc = check_topk(c, k);
+    if (rc) return rc;
+    wmd_query_options o;
+    if ((rc = wmd::check_query_options(opt, &o))) return rc;
+    std::vector<PlannedQuery> qs(1);
+    if ((rc = plan_query(c, qids, qweights, n, lambda, iters, o.precision == WMD_DIST_BF16, &qs[0]))) return rc;
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard guard(c->dc.device);
+    if (!guard.ok()) return fail(WMD_EDEVICE, "top-k: cannot select device");
+    const hipStream_t s = (hipStream_t)stream;
+    double dummy = 0.0;
+    int slot = 0;
+    if ((rc = run_queries(c, qs, o, &dummy, nullptr, s, true, &slot))) return rc;
+    Workspace& w = c->ws[slot];
+    int32_t* ri = nullptr;
+    double* rd = nullptr;
+    if ((rc = enqueue_topk(c, w, k, s, &ri, &rd))) return rc;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(dev_dist, rd, sizeof(double) * k, hipMemcpyDeviceToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(dev_idx, ri, sizeof(int32_t) * k, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+        return hip_fail(e, "top-k: copy results");
+    if ((e = hipEventRecord(w.done, s)) != hipSuccess) return hip_fail(e, "top-k: record");
+    return WMD_OK;
 }
 
 int wmd_set_timing(wmd_corpus* c, int32_t enable) {

@@ -36,6 +36,10 @@ struct Workspace {
     size_t ocap = 0;          // bytes
     double* h_out = nullptr;  // pinned copy of `out`
     size_t hocap = 0;
+    char* tk = nullptr;       // top-k scratch and results (device)
+    size_t tkcap = 0;
+    char* tk_host = nullptr;  // pinned top-k results
+    size_t tkhcap = 0;
     hipEvent_t done = nullptr;
     bool done_valid = false;
     hipStream_t last_stream = nullptr;   // stream of the slot's previous call

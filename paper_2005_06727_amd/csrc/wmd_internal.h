@@ -89,6 +89,12 @@ hipError_t launch_gather_rows(const float* vecs, const int32_t* ids, float* out,
 // receives the row minima and a second pass turns Kt into exp(-lambda (d - n)).
 hipError_t launch_dist(const DevCorpus& c, const QueryDev* qd, const int32_t* kofs, int B, int ncols, int bf16,
                        int shift, float* nrow_all, hipStream_t s);
+// k smallest (distance, index) pairs of n distances, ascending; scratch of
+// topk_scratch_bytes(n, k) device bytes.  k <= kMaxTopK.
+constexpr int kMaxTopK = WMD_MAX_TOPK;
+size_t topk_scratch_bytes(int64_t n, int k);
+hipError_t launch_topk(const double* dist, int64_t n, int k, void* scratch, size_t scratch_bytes, int32_t* res_idx,
+                       double* res_dist, hipStream_t s);
 // K1 for one short query whose parameter block (at most kUploadChunkBytes, host
 // image with device pointers) travels as kernel arguments; block 0 stores it
 // at params_dev for the launches that follow.  hq: the query's fields.

@@ -101,6 +101,10 @@ _sig("wmd_query_batch", C.c_int, _P, C.c_int32, _i64p, _i32p, _f32p, _f32p, _i32
      C.POINTER(wmd_query_options), _f64p, _f64p)
 _sig("wmd_query_batch_async", C.c_int, _P, C.c_int32, _i64p, _i32p, _f32p, _f32p, _i32p,
      C.POINTER(wmd_query_options), _P, _P, _P)
+_sig("wmd_query_topk", C.c_int, _P, _i32p, _f32p, C.c_int32, C.c_float, C.c_int32,
+     C.POINTER(wmd_query_options), C.c_int32, _i32p, _f64p)
+_sig("wmd_query_topk_async", C.c_int, _P, _i32p, _f32p, C.c_int32, C.c_float, C.c_int32,
+     C.POINTER(wmd_query_options), C.c_int32, _P, _P, _P)
 _sig("wmd_set_timing", C.c_int, _P, C.c_int32)
 _sig("wmd_timing_get", C.c_int, _P, C.POINTER(wmd_timing))
 _sig("wmd_server_options_init", None, C.POINTER(wmd_server_options))
@@ -264,6 +268,34 @@ def wmd_query_batch_async(corpus: int, queries, lambdas, iters, dev_dist, dev_re
                                       C.byref(o), _devptr(dev_dist), _devptr(dev_resid), _stream(stream)))
 
 
+WMD_MAX_TOPK = 2048
+
+
+def wmd_query_topk(corpus: int, qids, qweights, lam: float, iters: int, k: int, **opts):
+    """(indices, distances) of the k nearest documents, ascending by (distance, index)."""
+    q, w = _arr(qids, np.int32), _arr(qweights, np.float32)
+    if q.shape != w.shape or q.ndim != 1:
+        raise ValueError("query ids and weights must be 1-D of equal length")
+    idx = np.empty(max(int(k), 0), np.int32)
+    dist = np.empty(max(int(k), 0), np.float64)
+    o = _qopts(**opts)
+    _check(_lib.wmd_query_topk(corpus, _ptr(q, C.c_int32), _ptr(w, C.c_float), q.size, float(lam), int(iters),
+                               C.byref(o), int(k), _ptr(idx, C.c_int32), _ptr(dist, C.c_double)))
+    return idx, dist
+
+
+def wmd_query_topk_async(corpus: int, qids, qweights, lam: float, iters: int, k: int, dev_idx, dev_dist,
+                         stream=None, **opts) -> None:
+    q, w = _arr(qids, np.int32), _arr(qweights, np.float32)
+    o = _qopts(**opts)
+    if torch is not None and isinstance(dev_idx, torch.Tensor):
+        if not dev_idx.is_cuda or dev_idx.dtype != torch.int32 or not dev_idx.is_contiguous():
+            raise ValueError("dev_idx must be a contiguous int32 GPU tensor")
+        dev_idx = dev_idx.data_ptr()
+    _check(_lib.wmd_query_topk_async(corpus, _ptr(q, C.c_int32), _ptr(w, C.c_float), q.size, float(lam),
+                                     int(iters), C.byref(o), int(k), dev_idx, _devptr(dev_dist), _stream(stream)))
+
+
 def wmd_set_timing(corpus: int, every) -> None:
     """every: False/0 off, True/1 every call, k: every k-th call."""
     _check(_lib.wmd_set_timing(corpus, int(every)))
@@ -339,6 +371,9 @@ class Corpus:
 
     def query_batch(self, queries, lambdas, iters, resid=False, **opts):
         return wmd_query_batch(self.handle, queries, lambdas, iters, resid, **opts)
+
+    def topk(self, qids, qweights, lam, iters, k, **opts):
+        return wmd_query_topk(self.handle, qids, qweights, lam, iters, k, **opts)
 
     def close(self):
         if getattr(self, "handle", None):
