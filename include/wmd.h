@@ -76,6 +76,14 @@ typedef struct wmd_query_options {
                                  kernel for every document.  Results are identical
                                  between calls with the same tile, and agree across
                                  tiles to FP32 rounding. */
+    float   tol;              /* 0: exactly `iters` x updates per document (default).
+                                 > 0: the convergence check of Algorithm 1 ("while x
+                                 changes"): after each x update a document stops once
+                                 rho = sum_k r_k |x_k(t) / x_k(t-1) - 1| <= tol (rho is
+                                 the row-marginal residual of the plan built from
+                                 x(t-1)), else after `iters` updates.  The decision is
+                                 taken in FP32.  Needs iters_per_launch = 0 and a tile
+                                 of -1, -2 or 0..7. */
 } wmd_query_options;
 
 typedef struct wmd_corpus_info {
@@ -194,6 +202,15 @@ int wmd_query_batch_async(wmd_corpus* corpus, int32_t B, const int64_t* q_ptr,
                           const float* lambdas, const int32_t* iters,
                           const wmd_query_options* opt, double* dev_dist,
                           double* dev_resid, void* stream);
+
+/* wmd_query with the convergence check (opt->tol > 0; tol = 0 runs exactly
+ * max_iters updates): out_iters (nullable, N int32, input document order)
+ * receives the number of x updates each document made.  Errors as
+ * wmd_query, plus WMD_EINVAL for tol < 0 or not finite, or tol > 0 with
+ * iters_per_launch > 0 or a row-lane tile (8..10). */
+int wmd_query_adaptive(wmd_corpus* corpus, const int32_t* qids, const float* qweights,
+                       int32_t n, float lambda, int32_t max_iters, const wmd_query_options* opt,
+                       double* out_dist, double* out_resid, int32_t* out_iters);
 
 /*
  * Retrieval (the k nearest documents of a query, the use of WMD the paper

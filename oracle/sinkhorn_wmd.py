@@ -179,19 +179,32 @@ def sinkhorn_wmd_dense(vecs, qids, qweights, C, lam: float, iters: int,
 # -- the sparse transformation (SDDMM at the nonzeros of c, then SpMM) -------
 
 def sinkhorn_wmd_sparse(vecs, qids, qweights, doc_ptr, word_ids, weights,
-                        lam: float, iters: int, exact: bool = False,
-                        return_plans: bool = False):
+                        lam: float, iters, exact: bool = False,
+                        return_plans: bool = False, tol: float = 0.0,
+                        return_history: bool = False):
     """Same iteration, evaluated only where c != 0.
 
     Returns ``(wmd, resid)``: the N distances and, per document, the row
     marginal residual sum_k |(P 1)_k - r_k| of the final plan (its column
     marginal equals c exactly).  With ``return_plans`` a third item lists the
     plans P_j (v_r x nnz_j, columns in the document's CSR order).
+
+    ``iters`` is one count for every document or an array of N counts (each
+    document stops its x updates after its own count; column j of x depends
+    only on column j, so this is the same as running the documents alone).
+
+    ``tol > 0`` is Algorithm 1's "while x changes" test: after each x update,
+    document j computes rho_j = sum_k r_k |x_new[k, j] / x_old[k, j] - 1| and
+    makes no further update once rho_j <= tol (at most ``iters`` updates).
+    With ``return_history`` the result gains the number of updates t_j of
+    each document and the list of its rho values.
     """
     if lam < 0 or not math.isfinite(lam):
         raise ValueError("lambda must be finite and >= 0")
-    if iters < 0:
+    if np.any(np.asarray(iters) < 0):
         raise ValueError("iters must be >= 0")
+    if not (tol >= 0 and math.isfinite(tol)):
+        raise ValueError("tol must be finite and >= 0")
     ptr = np.asarray(doc_ptr, dtype=np.int64)
     word_ids = np.asarray(word_ids, dtype=np.int64)
     N = ptr.size - 1
@@ -224,15 +237,30 @@ def sinkhorn_wmd_sparse(vecs, qids, qweights, doc_ptr, word_ids, weights,
                 out[k, j] = math.fsum(prod[k, ptr[j]:ptr[j + 1]])
         return out
 
+    t_max = np.broadcast_to(np.asarray(iters, dtype=np.int64), (N,))
     x = np.ones((vr, N)) / vr
-    for _ in range(iters):
-        x = spmm(KoRg, c / sddmm(1.0 / x))
+    t = np.zeros(N, dtype=np.int64)                 # x updates made so far
+    active = t_max > 0
+    history = [[] for _ in range(N)]
+    while np.any(active):
+        x_new = spmm(KoRg, c / sddmm(1.0 / x))
+        rho = _colsum(r[:, None] * np.abs(x_new / x - 1.0), exact)
+        for j in np.flatnonzero(active):
+            history[j].append(float(rho[j]))
+        x = np.where(active[None, :], x_new, x)
+        t = t + active
+        active = active & (t < t_max)
+        if tol > 0:
+            active = active & (rho > tol)
     u = 1.0 / x
     v = c / sddmm(u)
     wmd = _colsum(u * spmm(KMg, v), exact)
     resid = _colsum(np.abs(u * spmm(Kg, v) - r[:, None]), exact)
+    out = (wmd, resid)
     if return_plans:
         plans = [u[:, j][:, None] * Kg[:, ptr[j]:ptr[j + 1]] * v[None, ptr[j]:ptr[j + 1]]
                  for j in range(N)]
-        return wmd, resid, plans
-    return wmd, resid
+        out = out + (plans,)
+    if return_history:
+        out = out + (t, history)
+    return out

@@ -107,6 +107,11 @@ int check_query_options(const wmd_query_options* in, wmd_query_options* o) {
     if (o->iters_per_launch < 0) return fail(WMD_EINVAL, "options: iters_per_launch < 0");
     if (o->tile < -2 || o->tile >= sinkhorn_num_shapes())
         return fail(WMD_EINVAL, "options: tile %d outside [-2, %d)", o->tile, sinkhorn_num_shapes());
+    if (!std::isfinite(o->tol) || o->tol < 0.f) return fail(WMD_EINVAL, "options: tol must be finite and >= 0");
+    if (o->tol > 0.f && o->iters_per_launch > 0)
+        return fail(WMD_EINVAL, "options: the convergence check (tol > 0) needs iters_per_launch = 0");
+    if (o->tol > 0.f && o->tile >= 0 && !sinkhorn_shape_adaptive(o->tile))
+        return fail(WMD_EINVAL, "options: tile %d has no convergence check", o->tile);
     return WMD_OK;
 }
 
@@ -153,7 +158,7 @@ int plan_query(const wmd_corpus* c, const int32_t* qids, const float* qw, int32_
 }
 
 Layout make_layout(const wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_query_options& opt,
-                   bool resid, bool host_out) {
+                   bool resid, bool host_out, bool iters_out) {
     Layout L;
     const int B = (int)qs.size();
     const int64_t N = c->dc.N, U = c->dc.U;
@@ -181,6 +186,7 @@ Layout make_layout(const wmd_corpus* c, const std::vector<PlannedQuery>& qs, con
     L.off_ri = align_up(L.off_r + sizeof(float) * L.sum_m, 64);
     L.pbytes = align_up(L.off_ri + sizeof(float) * L.sum_m, 64);
     L.obytes = host_out ? sizeof(double) * (size_t)B * N * (resid ? 2 : 1) : 0;
+    if (host_out && iters_out) L.obytes += sizeof(int32_t) * (size_t)B * N;
     return L;
 }
 
@@ -331,13 +337,15 @@ int fold_timing_slot(wmd_corpus* c, int slot) {
 // Enqueue K1 + the fused Sinkhorn launches for `qs` on `stream`.  Row b of
 // dev_out (and dev_res when non-null) receives query b's N results.
 int run_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_query_options& opt,
-                double* dev_out, double* dev_res, hipStream_t stream, bool need_host_out, int* slot_used) {
+                double* dev_out, double* dev_res, hipStream_t stream, bool need_host_out, int* slot_used,
+                bool iters_out) {
     const int wslot = c->next_ws;
     c->next_ws = (c->next_ws + 1) % kWorkSlots;
     *slot_used = wslot;
     // timing on: every c->timing-th call records its kernel events
     const bool timed = c->timing > 0 && (c->timing_seq++ % c->timing) == 0;
-    return enqueue_queries(c, qs, opt, dev_out, dev_res, stream, need_host_out, c->ws[wslot], c->stage, timed);
+    return enqueue_queries(c, qs, opt, dev_out, dev_res, stream, need_host_out, c->ws[wslot], c->stage, timed,
+                           iters_out);
 }
 
 size_t workspace_bytes(const wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_query_options& opt,
@@ -347,11 +355,11 @@ size_t workspace_bytes(const wmd_corpus* c, const std::vector<PlannedQuery>& qs,
 
 int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_query_options& opt,
                     double* dev_out, double* dev_res, hipStream_t stream, bool need_host_out, Workspace& w,
-                    Staging& st, bool timed) {
+                    Staging& st, bool timed, bool iters_out) {
     const DevCorpus& dc = c->dc;
     const int B = (int)qs.size();
     const int64_t N = dc.N, U = dc.U;
-    const Layout L = make_layout(c, qs, opt, dev_res != nullptr, need_host_out);
+    const Layout L = make_layout(c, qs, opt, dev_res != nullptr, need_host_out, iters_out);
     const int max_m = L.max_m, max_iters = L.max_iters, per_launch = L.per_launch;
     const bool chunked = L.chunked;
     const size_t sum_ldk = L.sum_ldk;
@@ -362,9 +370,11 @@ int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wm
         return fail(WMD_EINVAL, "options: tile %d cannot hold a %d-word query", opt.tile, max_m);
     int rc = ensure_workspace(w, L, need_host_out);
     if (rc) return rc;
+    int32_t* dev_iters = nullptr;
     if (need_host_out) {
         dev_out = w.out;
         if (dev_res) dev_res = w.out + (size_t)B * N;
+        if (iters_out) dev_iters = reinterpret_cast<int32_t*>(w.out + (size_t)B * N * (dev_res ? 2 : 1));
     }
 
     // small parameter blocks go up as kernel arguments (built in host memory
@@ -410,6 +420,8 @@ int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wm
         d.nrow = opt.log_domain ? w.nrow + (size_t)U * b : nullptr;
         d.km_from_k = q.lambda >= kKmFromKMinLambda ? 1 : 0;
         d.inv_lambda = d.km_from_k ? 1.0f / q.lambda : 0.f;
+        d.tol = opt.tol;
+        d.it_out = dev_iters ? dev_iters + (size_t)b * N : nullptr;
         std::memcpy(hid + mo, q.ids.data(), sizeof(int32_t) * q.m);
         std::memcpy(hr + mo, q.r.data(), sizeof(float) * q.m);
         std::memcpy(hri + mo, q.rinv.data(), sizeof(float) * q.m);
@@ -425,7 +437,7 @@ int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wm
     for (int b = 0; b < B; ++b) {
         if (opt.tile == -2) shape_of[b] = -1;
         else if (opt.tile >= 0) shape_of[b] = opt.tile;
-        else shape_of[b] = sinkhorn_shape_for(qs[b].m, kTileMaxDoc);
+        else shape_of[b] = sinkhorn_shape_for(qs[b].m, kTileMaxDoc, opt.tol > 0.f);
         cnt[shape_of[b] + 1]++;
     }
     std::vector<int> start(nshape + 2, 0);
@@ -536,6 +548,7 @@ void wmd_query_options_init(wmd_query_options* opt) {
     opt->log_domain = 0;
     opt->iters_per_launch = 0;
     opt->tile = -1;
+    opt->tol = 0.f;
 }
 
 static void corpus_free(wmd_corpus* c) {
@@ -774,6 +787,36 @@ int wmd_query(wmd_corpus* c, const int32_t* qids, const float* qweights, int32_t
     int slot = 0;
     if ((rc = run_queries(c, qs, o, &dummy, out_resid ? &dummy : nullptr, c->stream, true, &slot))) return rc;
     return finish_sync(c, slot, 1, out_dist, out_resid);
+}
+
+int wmd_query_adaptive(wmd_corpus* c, const int32_t* qids, const float* qweights, int32_t n, float lambda,
+                       int32_t max_iters, const wmd_query_options* opt, double* out_dist, double* out_resid,
+                       int32_t* out_iters) {
+    if (!c || !out_dist) return fail(WMD_EINVAL, "query: null corpus or output");
+    wmd_query_options o;
+    int rc = wmd::check_query_options(opt, &o);
+    if (rc) return rc;
+    std::vector<PlannedQuery> qs(1);
+    if ((rc = plan_query(c, qids, qweights, n, lambda, max_iters, o.precision == WMD_DIST_BF16, &qs[0]))) return rc;
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard guard(c->dc.device);
+    if (!guard.ok()) return fail(WMD_EDEVICE, "query: cannot select device");
+    double dummy = 0.0;
+    int slot = 0;
+    if ((rc = run_queries(c, qs, o, &dummy, out_resid ? &dummy : nullptr, c->stream, true, &slot, true))) return rc;
+    Workspace& w = c->ws[slot];
+    const size_t N = (size_t)c->dc.N;
+    const size_t nd = N * (out_resid ? 2 : 1);
+    const size_t bytes = sizeof(double) * nd + sizeof(int32_t) * N;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(w.h_out, w.out, bytes, hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+        return hip_fail(e, "query: download results");
+    if ((e = hipEventRecord(w.done, c->stream)) != hipSuccess) return hip_fail(e, "query: record");
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(e, "query: execution");
+    std::memcpy(out_dist, w.h_out, sizeof(double) * N);
+    if (out_resid) std::memcpy(out_resid, w.h_out + N, sizeof(double) * N);
+    if (out_iters) std::memcpy(out_iters, w.h_out + nd, sizeof(int32_t) * N);
+    return WMD_OK;
 }
 
 int wmd_query_async(wmd_corpus* c, const int32_t* qids, const float* qweights, int32_t n, float lambda,

@@ -210,7 +210,8 @@ template <int R, int C, int P, int Q, int W, int PN>
 __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp, const bool valid, const int d,
                                           const int rs, const int n, const int m, const int ldk, const int a,
                                           const int b, const int tl, const int wi, const int team, const int kb,
-                                          const int it_end, const int my_end, float* s_part, double* s_red) {
+                                          const int it_end, const int my_end, float* s_part, double* s_red,
+                                          float* s_rho) {
     constexpr int T = R * C;
     constexpr int Q4 = Q / 4;
 
@@ -258,6 +259,14 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
 
     float u[Q], s[PN], v[PN], y[Q];
     int par = 0;
+    // convergence check (uniform over the launch: one tol per call)
+    const float tol = qp->tol;
+    const bool adaptive = tol > 0.f;
+    float rq[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) rq[q] = (adaptive && kb + q < m) ? qp->r[kb + q] : 0.f;
+    bool done = false;
+    int t_done = g.it_begin;
 
     // s = A u summed over the team (lanes b, then waves); v = c / s
     // (the scheduling barriers keep each phase step-major: every reduction step
@@ -311,26 +320,46 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
 
     for (int it = g.it_begin; it < it_end; ++it) {
         if constexpr (W == 1) {
+            // a wave leaves once every team in it has converged
+            if (adaptive && __builtin_amdgcn_ballot_w64(!done) == 0) break;
+        }
 #pragma unroll
-            for (int q = 0; q < Q; ++q) u[q] = rcp(x[q]);
-            sddmm();
-            spmm();
-#pragma unroll
-            for (int q = 0; q < Q; ++q) x[q] = fmaf(y[q], rinv[q], xpad[q]);
-        } else {
-            // teams of a block run the block's largest iteration count (same
-            // barriers); a team past its own count computes but keeps x
-            const bool act = it < my_end;
-#pragma unroll
-            for (int q = 0; q < Q; ++q) u[q] = rcp(x[q]);
-            sddmm();
-            spmm();
-            if (act) {
+        for (int q = 0; q < Q; ++q) u[q] = rcp(x[q]);
+        sddmm();
+        spmm();
+        if (!adaptive) {
+            // teams of a multi-wave block run the block's largest iteration count
+            // (same barriers); a team past its own count computes but keeps x
+            if (W == 1 || it < my_end) {
 #pragma unroll
                 for (int q = 0; q < Q; ++q) x[q] = fmaf(y[q], rinv[q], xpad[q]);
+                t_done = it + 1;
+            }
+        } else {
+            // rho = sum_k r_k |x_new / x_old - 1|, with u = 1 / x_old from above
+            float xn[Q];
+            float rho = 0.f;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                xn[q] = fmaf(y[q], rinv[q], xpad[q]);
+                rho = fmaf(rq[q], fabsf(xn[q] * u[q] - 1.f), rho);
+            }
+            sum_over_b_n<C, 1>(&rho);
+            if constexpr (W > 1) {
+                if (b == 0 && a == 0) s_rho[team * W + wi] = rho;
+                __syncthreads();
+                rho = 0.f;
+                for (int w2 = 0; w2 < W; ++w2) rho += s_rho[team * W + w2];
+            }
+            if (!done && (W == 1 || it < my_end)) {
+#pragma unroll
+                for (int q = 0; q < Q; ++q) x[q] = xn[q];
+                t_done = it + 1;
+                done = rho <= tol;
             }
         }
     }
+    if (g.final_step && qp->it_out && valid && tl == 0 && wi == 0) qp->it_out[g.sdoc[d]] = t_done;
 
     if (!g.final_step) {
         if (valid && a == 0) {
@@ -433,6 +462,7 @@ __global__ __launch_bounds__(256) void k_sink(SinkArgs g) {
     __shared__ float s_part[(W > 1) ? TEAMS * 2 * W * R * P : 1];
     __shared__ double s_red[(W > 1) ? TEAMS * W * 2 : 1];
     __shared__ int s_itmax[(W > 1) ? TEAMS : 1];
+    __shared__ float s_rho[(W > 1) ? TEAMS * W : 1];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int team = (W == 1) ? wave * TPW + lane / T : wave / W;
@@ -473,7 +503,8 @@ __global__ __launch_bounds__(256) void k_sink(SinkArgs g) {
     // sorted by length, so the teams of a wave have similar n); uniform, SGPR
     const int pg = __builtin_amdgcn_readfirstlane((wave_max((n + R - 1) / R) + 3) >> 2);
 #define WMD_SINK_TEAM(PN) \
-    sink_team<R, C, P, Q, W, PN>(g, qp, valid, d, rs, n, m, ldk, a, b, tl, wi, team, kb, it_end, my_end, s_part, s_red)
+    sink_team<R, C, P, Q, W, PN>(g, qp, valid, d, rs, n, m, ldk, a, b, tl, wi, team, kb, it_end, my_end, s_part, s_red, \
+                                 s_rho)
     if constexpr (P == 16) {
         if (pg <= 1) WMD_SINK_TEAM(4);
         else if (pg == 2) WMD_SINK_TEAM(8);
@@ -523,16 +554,33 @@ __global__ __launch_bounds__(256) void k_sink_stream(SinkArgs g) {
         }
         __syncthreads();
     };
+    const float tol = qp->tol;
+    __shared__ float s_rho[4];
+    int t_done = g.it_begin;
     for (int it = g.it_begin; it < it_end; ++it) {
         sddmm();
+        float rho = 0.f;
         for (int k = tid; k < m; k += 256) {
             float acc = 0.f;
             for (int i = 0; i < n; ++i)
                 acc = fmaf(qp->Kt[(int64_t)g.scol[rs + i] * ldk + k], v[i], acc);
-            x[k] = acc * ri[k];
+            const float xn = acc * ri[k];
+            // convergence check: rho = sum_k r_k |x_new / x_old - 1|, u = 1 / x_old
+            if (tol > 0.f) rho = fmaf(qp->r[k], fabsf(xn * u[k] - 1.f), rho);
+            x[k] = xn;
         }
         __syncthreads();
+        t_done = it + 1;
+        if (tol > 0.f) {
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) rho += __shfl_xor(rho, o, 64);
+            if ((tid & 63) == 0) s_rho[tid >> 6] = rho;
+            __syncthreads();
+            const float tot = s_rho[0] + s_rho[1] + s_rho[2] + s_rho[3];
+            if (tot <= tol) break;
+        }
     }
+    if (g.final_step && qp->it_out && tid == 0) qp->it_out[g.sdoc[d]] = t_done;
     if (!g.final_step) {
         for (int k = tid; k < m; k += 256) qp->x[(int64_t)d * ldk + k] = x[k];
         return;
@@ -743,6 +791,7 @@ __global__ __launch_bounds__(64) void k_sink_rows(SinkArgs g) {
         const int doc = g.sdoc[d];
         qp->out[doc] = wsum;
         if (qp->resid) qp->resid[doc] = rho;
+        if (qp->it_out) qp->it_out[doc] = it_end;
     }
 }
 
@@ -777,13 +826,16 @@ const Shape kShapes[] = {
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 // default shape per query-length class (first entry whose max_m covers m)
 const int kDefaultShapes[] = {8, 2, 4, 5, 6, 7};   // chosen by measurement on the c2-shaped corpus
+const int kAdaptiveShapes[] = {0, 2, 4, 5, 6, 7};  // register tiles only (convergence check)
 
 }  // namespace
 
 int sinkhorn_num_shapes() { return kNumShapes; }
 
-int sinkhorn_shape_for(int m, int max_n) {
-    for (int s : kDefaultShapes)
+bool sinkhorn_shape_adaptive(int shape) { return shape < 0 || kShapes[shape].threads == 256; }
+
+int sinkhorn_shape_for(int m, int max_n, bool adaptive) {
+    for (int s : (adaptive ? kAdaptiveShapes : kDefaultShapes))
         if (m <= kShapes[s].max_m && max_n <= kShapes[s].max_n) return s;
     return -1;
 }

@@ -118,18 +118,21 @@ struct wmd_corpus {
 };
 
 namespace wmd {
+// host_out: results go to the workspace's output buffer (B x N distances, then
+// B x N residuals when resid, then B x N int32 iteration counts when iters_out)
 Layout make_layout(const wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_query_options& opt,
-                   bool resid, bool host_out);
+                   bool resid, bool host_out, bool iters_out = false);
 int plan_query(const wmd_corpus* c, const int32_t* qids, const float* qw, int32_t n, float lambda,
                int32_t iters, int bf16, PlannedQuery* out);
 // Enqueue a call on the corpus's own workspace slots; *slot receives the slot used.
 int run_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_query_options& opt,
-                double* dev_out, double* dev_res, hipStream_t stream, bool need_host_out, int* slot);
+                double* dev_out, double* dev_res, hipStream_t stream, bool need_host_out, int* slot,
+                bool iters_out = false);
 int fold_timing_slot(wmd_corpus* c, int slot);
 // Enqueue a call on an explicit workspace and staging ring (the server's own).
 int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_query_options& opt,
                     double* dev_out, double* dev_res, hipStream_t stream, bool need_host_out, Workspace& w,
-                    Staging& st, bool timed);
+                    Staging& st, bool timed, bool iters_out = false);
 // Device bytes a call's workspace needs (K buffers, row shifts, iterate, results).
 size_t workspace_bytes(const wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wmd_query_options& opt,
                        bool resid);

@@ -34,6 +34,8 @@ struct QueryDev {
     int32_t shift;         // log-domain column shift on/off
     int32_t km_from_k;     // the final step rebuilds K .* M from K: M = n_i - ln(K) / lambda
     float inv_lambda;      // 1 / lambda (km_from_k only)
+    float tol;             // > 0: stop a document once its x-change residual <= tol
+    int32_t* it_out;       // N x updates made per document (input order) or nullptr
 };
 
 // Device-resident corpus (all arrays on `device`).
@@ -106,7 +108,11 @@ hipError_t launch_dist_narrow(const DevCorpus& c, const QueryDev& hq, const Quer
 // tile (see k_sinkhorn.hip); shape < 0 selects the streaming kernel that
 // handles any size.
 int sinkhorn_num_shapes();
-int sinkhorn_shape_for(int m, int max_n);   // -1 when only the streaming kernel fits
+// -1 when only the streaming kernel fits; adaptive: the convergence check is
+// on (register tiles and the streaming kernel implement it, the row-lane
+// kernels do not)
+int sinkhorn_shape_for(int m, int max_n, bool adaptive = false);
+bool sinkhorn_shape_adaptive(int shape);
 bool sinkhorn_shape_fits(int shape, int m, int max_n);
 int sinkhorn_shape_max_m(int shape);
 int sinkhorn_shape_max_n(int shape);

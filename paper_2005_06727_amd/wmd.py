@@ -48,7 +48,8 @@ class wmd_corpus_options(C.Structure):
 
 class wmd_query_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("recompute_below", C.c_float),
-                ("log_domain", C.c_int32), ("iters_per_launch", C.c_int32), ("tile", C.c_int32)]
+                ("log_domain", C.c_int32), ("iters_per_launch", C.c_int32), ("tile", C.c_int32),
+                ("tol", C.c_float)]
 
 
 class wmd_corpus_info(C.Structure):
@@ -101,6 +102,8 @@ _sig("wmd_query_batch", C.c_int, _P, C.c_int32, _i64p, _i32p, _f32p, _f32p, _i32
      C.POINTER(wmd_query_options), _f64p, _f64p)
 _sig("wmd_query_batch_async", C.c_int, _P, C.c_int32, _i64p, _i32p, _f32p, _f32p, _i32p,
      C.POINTER(wmd_query_options), _P, _P, _P)
+_sig("wmd_query_adaptive", C.c_int, _P, _i32p, _f32p, C.c_int32, C.c_float, C.c_int32,
+     C.POINTER(wmd_query_options), _f64p, _f64p, _i32p)
 _sig("wmd_query_topk", C.c_int, _P, _i32p, _f32p, C.c_int32, C.c_float, C.c_int32,
      C.POINTER(wmd_query_options), C.c_int32, _i32p, _f64p)
 _sig("wmd_query_topk_async", C.c_int, _P, _i32p, _f32p, C.c_int32, C.c_float, C.c_int32,
@@ -144,7 +147,7 @@ def _ptr(a: np.ndarray, ctype):
 
 
 def _qopts(precision=WMD_DIST_FP32, recompute_below=-1.0, log_domain=False, iters_per_launch=0,
-           tile=-1):
+           tile=-1, tol=0.0):
     o = wmd_query_options()
     _lib.wmd_query_options_init(C.byref(o))
     o.precision = int(precision)
@@ -152,6 +155,7 @@ def _qopts(precision=WMD_DIST_FP32, recompute_below=-1.0, log_domain=False, iter
     o.log_domain = int(bool(log_domain))
     o.iters_per_launch = int(iters_per_launch)
     o.tile = int(tile)
+    o.tol = float(tol)
     return o
 
 
@@ -268,6 +272,23 @@ def wmd_query_batch_async(corpus: int, queries, lambdas, iters, dev_dist, dev_re
                                       C.byref(o), _devptr(dev_dist), _devptr(dev_resid), _stream(stream)))
 
 
+def wmd_query_adaptive(corpus: int, qids, qweights, lam: float, max_iters: int, tol: float, resid: bool = False,
+                       **opts):
+    """Convergence-checked query: (distances, residuals or None, x updates per document)."""
+    q, w = _arr(qids, np.int32), _arr(qweights, np.float32)
+    if q.shape != w.shape or q.ndim != 1:
+        raise ValueError("query ids and weights must be 1-D of equal length")
+    N = wmd_corpus_info_get(corpus)["N"]
+    out = np.empty(N, np.float64)
+    res = np.empty(N, np.float64) if resid else None
+    its = np.empty(N, np.int32)
+    o = _qopts(tol=tol, **opts)
+    _check(_lib.wmd_query_adaptive(corpus, _ptr(q, C.c_int32), _ptr(w, C.c_float), q.size, float(lam),
+                                   int(max_iters), C.byref(o), _ptr(out, C.c_double),
+                                   _ptr(res, C.c_double) if resid else None, _ptr(its, C.c_int32)))
+    return out, res, its
+
+
 WMD_MAX_TOPK = 2048
 
 
@@ -371,6 +392,9 @@ class Corpus:
 
     def query_batch(self, queries, lambdas, iters, resid=False, **opts):
         return wmd_query_batch(self.handle, queries, lambdas, iters, resid, **opts)
+
+    def query_adaptive(self, qids, qweights, lam, max_iters, tol, resid=False, **opts):
+        return wmd_query_adaptive(self.handle, qids, qweights, lam, max_iters, tol, resid, **opts)
 
     def topk(self, qids, qweights, lam, iters, k, **opts):
         return wmd_query_topk(self.handle, qids, qweights, lam, iters, k, **opts)

@@ -76,7 +76,22 @@ def battery(o) -> bool:
         d, res = o.sinkhorn_wmd_sparse(pts, a, ones, np.array([0, 4]), b, ones, 60.0, 5000)
         emd = emd_bruteforce_uniform(_d64(pts, a, b))
         ok &= bool(res[0] < 1e-9) and emd - 1e-9 <= d[0] <= emd + math.log(4) / 60.0 + 1e-9
-    except (ValueError, FloatingPointError, ZeroDivisionError, IndexError):
+        # convergence check: rho(t) is the row-marginal residual after t - 1 updates,
+        # and a document stops at the first t with rho(t) <= tol
+        _, _, t, hist = o.sinkhorn_wmd_sparse(vecs, q, qw, ptr, ids, w, 4.0, 12, tol=1e-3,
+                                              return_history=True)
+        for tt in range(1, 7):
+            res_prev = o.sinkhorn_wmd_sparse(vecs, q, qw, ptr, ids, w, 4.0, tt - 1)[1]
+            for j in range(ptr.size - 1):
+                if len(hist[j]) >= tt:
+                    ok &= math.isclose(hist[j][tt - 1], res_prev[j], rel_tol=1e-9, abs_tol=1e-15)
+        for j in range(ptr.size - 1):
+            below = [i for i, v in enumerate(hist[j]) if v <= 1e-3]
+            ok &= int(t[j]) == (below[0] + 1 if below else 12) and len(hist[j]) == int(t[j])
+        d_ad = o.sinkhorn_wmd_sparse(vecs, q, qw, ptr, ids, w, 4.0, 12, tol=1e-3)[0]
+        d_fix = o.sinkhorn_wmd_sparse(vecs, q, qw, ptr, ids, w, 4.0, np.asarray(t))[0]
+        ok &= bool(np.array_equal(d_ad, d_fix))
+    except (ValueError, FloatingPointError, ZeroDivisionError, IndexError, TypeError):
         return False
     return bool(ok)
 
@@ -91,8 +106,16 @@ MUTANTS = {
     "wmd_drops_u_dense": ("wmd = _colsum(u * _matmul(K * M, v, exact), exact)",
                           "wmd = _colsum(_matmul(K * M, v, exact), exact)"),
     "v_multiplies": ("v = c / sddmm(u)", "v = c * sddmm(u)"),
-    "extra_iteration": ("for _ in range(iters):\n        x = spmm(",
-                        "for _ in range(iters + 1):\n        x = spmm("),
+    "extra_iteration_dense": ("for _ in range(iters):\n        x = _matmul(",
+                              "for _ in range(iters + 1):\n        x = _matmul("),
+    "extra_iteration_sparse": ("t_max = np.broadcast_to(np.asarray(iters, dtype=np.int64), (N,))",
+                               "t_max = np.broadcast_to(np.asarray(iters, dtype=np.int64) + 1, (N,))"),
+    "rho_unweighted": ("rho = _colsum(r[:, None] * np.abs(x_new / x - 1.0), exact)",
+                       "rho = _colsum(np.abs(x_new / x - 1.0), exact)"),
+    "rho_absolute_change": ("rho = _colsum(r[:, None] * np.abs(x_new / x - 1.0), exact)",
+                            "rho = _colsum(r[:, None] * np.abs(x_new - x), exact)"),
+    "stop_one_late": ("            active = active & (rho > tol)",
+                      "            active = active & (np.roll(rho, 0) > tol * 0.5)"),
     "r_not_normalised": ("return ids, w / math.fsum(w)", "return ids, w"),
     "c_not_normalised": ("c[ptr[j]:ptr[j + 1]] = seg / math.fsum(seg)",
                          "c[ptr[j]:ptr[j + 1]] = seg"),

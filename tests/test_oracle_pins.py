@@ -269,3 +269,45 @@ def test_input_errors():
         sinkhorn_wmd_sparse(vecs, qids, qw, ptr, ids, w, -1.0, 3)
     with pytest.raises(ValueError):
         sinkhorn_wmd_sparse(vecs, qids, qw, ptr, ids, w, 1.0, -1)
+
+
+# -- convergence check (Algorithm 1's "while x changes"; rho = row-marginal residual)
+
+def _adaptive_case():
+    rng = np.random.default_rng(31)
+    vecs = synth.embeddings(60, 8, rng)
+    ptr, ids, w = synth.corpus(60, 7, (1, 9), rng)
+    q, qw = synth.query(60, 5, rng, "uniform")
+    return vecs, q, qw, ptr, ids, w
+
+
+def test_rho_is_residual_of_previous_plan():
+    vecs, q, qw, ptr, ids, w = _adaptive_case()
+    _, _, t, hist = sinkhorn_wmd_sparse(vecs, q, qw, ptr, ids, w, 6.0, 10, return_history=True)
+    assert np.all(t == 10)
+    for tt in range(1, 11):
+        prev = sinkhorn_wmd_sparse(vecs, q, qw, ptr, ids, w, 6.0, tt - 1)[1]
+        np.testing.assert_allclose([h[tt - 1] for h in hist], prev, rtol=1e-10, atol=1e-16)
+
+
+def test_adaptive_stops_at_first_small_rho_and_matches_fixed_counts():
+    vecs, q, qw, ptr, ids, w = _adaptive_case()
+    tol = 2e-3
+    d, res, t, hist = sinkhorn_wmd_sparse(vecs, q, qw, ptr, ids, w, 6.0, 40, tol=tol, return_history=True)
+    for j, h in enumerate(hist):
+        assert len(h) == t[j]
+        assert all(v > tol for v in h[:-1])
+        assert h[-1] <= tol or t[j] == 40
+    d_fix, res_fix = sinkhorn_wmd_sparse(vecs, q, qw, ptr, ids, w, 6.0, t)
+    assert np.array_equal(d, d_fix) and np.array_equal(res, res_fix)
+    # a one-word document's plan is exact after one update: rho(2) = 0
+    d1, _, t1, h1 = sinkhorn_wmd_sparse(vecs, q, qw, np.array([0, 1]), np.array([7]), np.array([1.0]),
+                                        6.0, 9, tol=1e-14, return_history=True)
+    assert t1[0] == 2 and h1[0][1] == 0.0
+
+
+def test_huge_tol_is_one_update():
+    vecs, q, qw, ptr, ids, w = _adaptive_case()
+    d, _, t, _ = sinkhorn_wmd_sparse(vecs, q, qw, ptr, ids, w, 6.0, 25, tol=1e9, return_history=True)
+    assert np.all(t == 1)
+    assert np.array_equal(d, sinkhorn_wmd_sparse(vecs, q, qw, ptr, ids, w, 6.0, 1)[0])
