@@ -42,8 +42,10 @@ PEAK_FP32_MFMA_TFLOPS = 157.3    # MI355X dense FP32 matrix
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=1000)
-    p.add_argument("--warmup", type=int, default=50)
+    # the GPU's clocks ramp up over the first ~100 ms of load, so the default
+    # warm-up is a few thousand queries (well under a second)
+    p.add_argument("--steps", type=int, default=5000)
+    p.add_argument("--warmup", type=int, default=3000)
     p.add_argument("--workload", default="c2", choices=["c1", "c2"])
     p.add_argument("--latency-calls", type=int, default=300)
     p.add_argument("--no-cpu-baseline", action="store_true")
