@@ -57,6 +57,8 @@ def parse():
     p.add_argument("--queries", type=int, default=2000)
     p.add_argument("--qps", type=float, default=0.0, help="offered rate (0: 80%% of plain capacity)")
     p.add_argument("--max-batch", type=int, default=16)
+    p.add_argument("--streams", type=int, default=2, help="server streams (batches in flight)")
+    p.add_argument("--batch-words", type=int, default=512, help="server cap on query words per batch")
     p.add_argument("--hbm-budget-gib", type=float, default=16.0)
     return p.parse_args()
 
@@ -225,8 +227,8 @@ def serve_main(args):
     plain_rate = nprobe / (time.perf_counter() - t)
     print(f"# plain FP32 closed loop: {plain_rate:.1f} q/s", file=sys.stderr, flush=True)
     budget = int(args.hbm_budget_gib * (1 << 30))
-    kw = dict(hbm_budget_bytes=budget, max_batch=args.max_batch, max_inflight=2,
-              precision=wmd.WMD_DIST_BF16)
+    kw = dict(hbm_budget_bytes=budget, max_batch=args.max_batch, max_inflight=args.streams,
+              max_batch_words=args.batch_words, precision=wmd.WMD_DIST_BF16)
     with wmd.Server(corpus, **kw) as srv:
         t = time.perf_counter()
         ts = [srv.submit(q, w, lam, iters) for q, w in qs[:nprobe]]
@@ -250,7 +252,8 @@ def serve_main(args):
         "config": {"workload": f"{sp.name}: Poisson stream of {nq} queries, v_r log-uniform 3-500, "
                                f"V={sp.V}, dim={sp.dim}, N={N}, nnz={info['nnz']}, U={info['U']}, "
                                f"lambda={lam}, {iters} iterations",
-                   "qps": qps, "hbm_budget_bytes": budget, "max_batch": args.max_batch, "streams": 2},
+                   "qps": qps, "hbm_budget_bytes": budget, "max_batch": args.max_batch, "streams": args.streams,
+                   "max_batch_words": args.batch_words},
         "served": {"latency_ms": {"p50": st["latency_p50_ms"], "p99": st["latency_p99_ms"],
                                   "mean": st["latency_mean_ms"], "max": st["latency_max_ms"]},
                    "doc_iters_per_s": work / span, "mean_batch": st["mean_batch"],

@@ -261,7 +261,8 @@ int wmd_timing_get(wmd_corpus* corpus, wmd_timing* out);
  * workspace per stream, carved from `hbm_budget_bytes` (each stream gets an
  * equal share, allocated at creation).  Submitted queries wait in FIFO order;
  * whenever a stream is free the worker launches the longest FIFO prefix (at
- * most `max_batch` queries) whose workspace fits that stream's share, so
+ * most `max_batch` queries and `max_batch_words` query words) whose workspace
+ * fits that stream's share, so
  * batches admitted while others run overlap on the device.  Every query's
  * result is bitwise the one wmd_query returns for it with the same options:
  * a document's computation does not depend on the rest of the batch.
@@ -276,6 +277,9 @@ typedef struct wmd_server_options {
     int32_t batch_wait_us;     /* how long a lone waiting query may wait for others to
                                   batch with (0: launch at once) */
     wmd_query_options query;   /* options of every query */
+    int32_t max_batch_words;   /* cap on the query words of one batch (its work), so a
+                                  burst of queries does not form one long batch; a
+                                  query longer than the cap runs alone (0: no cap) */
 } wmd_server_options;
 
 typedef struct wmd_server_stats {
@@ -290,8 +294,8 @@ typedef struct wmd_server_stats {
     int64_t workspace_bytes;   /* device memory held by the server */
 } wmd_server_stats;
 
-/* Defaults: 4 GiB budget, batches of 16, 2 streams, no residuals, no batching
- * wait, default query options. */
+/* Defaults: 4 GiB budget, batches of 16 and at most 512 query words, 2
+ * streams, no residuals, no batching wait, default query options. */
 void wmd_server_options_init(wmd_server_options* opt);
 
 /* Create a server on `corpus` (which must outlive it).  Errors: WMD_EINVAL for

@@ -161,12 +161,16 @@ void worker_main(wmd_server* S) {
             // the longest FIFO prefix that fits this stream's share
             std::vector<PlannedQuery> qs;
             std::vector<int64_t> ids;
+            int64_t words = 0;
             while (!S->pending.empty() && (int)ids.size() < S->opt.max_batch) {
-                qs.push_back(S->tickets.at(S->pending.front()).q);
+                const PlannedQuery& nq = S->tickets.at(S->pending.front()).q;
+                if (!ids.empty() && S->opt.max_batch_words > 0 && words + nq.m > S->opt.max_batch_words) break;
+                qs.push_back(nq);
                 if (make_layout(S->corpus, qs, S->opt.query, resid, true).device_bytes() > sl->cap) {
                     qs.pop_back();
                     break;
                 }
+                words += nq.m;
                 ids.push_back(S->pending.front());
                 S->pending.pop_front();
             }
@@ -231,6 +235,7 @@ void wmd_server_options_init(wmd_server_options* opt) {
     opt->want_resid = 0;
     opt->batch_wait_us = 0;
     wmd_query_options_init(&opt->query);
+    opt->max_batch_words = 512;
 }
 
 int wmd_server_create(wmd_corpus* corpus, const wmd_server_options* opt_in, wmd_server** out) {
@@ -242,6 +247,7 @@ int wmd_server_create(wmd_corpus* corpus, const wmd_server_options* opt_in, wmd_
     if (opt.max_batch < 1) return fail(WMD_EINVAL, "server: max_batch must be >= 1");
     if (opt.max_inflight < 1 || opt.max_inflight > 16) return fail(WMD_EINVAL, "server: max_inflight outside 1..16");
     if (opt.batch_wait_us < 0) return fail(WMD_EINVAL, "server: batch_wait_us < 0");
+    if (opt.max_batch_words < 0) return fail(WMD_EINVAL, "server: max_batch_words < 0");
     wmd_query_options qo;
     int rc = check_query_options(&opt.query, &qo);
     if (rc) return rc;

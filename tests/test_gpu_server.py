@@ -39,12 +39,13 @@ def mixed_queries(V, n, seed, lo=1, hi=300):
     return out
 
 
-@pytest.mark.parametrize("max_inflight,max_batch", [(1, 1), (2, 8), (4, 16)])
-def test_served_equals_single_bitwise(ragged, wmd, max_inflight, max_batch):
+@pytest.mark.parametrize("max_inflight,max_batch,words", [(1, 1, 0), (2, 8, 0), (4, 16, 0), (2, 16, 100)])
+def test_served_equals_single_bitwise(ragged, wmd, max_inflight, max_batch, words):
     (vecs, ptr, ids, w), c = ragged
-    qs = mixed_queries(vecs.shape[0], 40, seed=max_batch)
+    qs = mixed_queries(vecs.shape[0], 40, seed=max_batch + words)
     lam, iters = 10.0, 12
-    with wmd.Server(c, max_inflight=max_inflight, max_batch=max_batch, want_resid=True) as s:
+    with wmd.Server(c, max_inflight=max_inflight, max_batch=max_batch, want_resid=True,
+                    max_batch_words=words) as s:
         tickets = [s.submit(q, qw, lam, iters) for q, qw in qs]
         served = [s.wait(t) for t in tickets]
         st = s.stats()
@@ -96,7 +97,7 @@ def test_budget_admission(ragged, wmd):
 def test_ticket_errors_and_options(ragged, wmd):
     (vecs, ptr, ids, w), c = ragged
     for kw in ({"max_inflight": 0}, {"max_inflight": 17}, {"max_batch": 0}, {"hbm_budget_bytes": 0},
-               {"batch_wait_us": -1}, {"tile": 3}, {"precision": wmd.WMD_DIST_BF16}):
+               {"batch_wait_us": -1}, {"max_batch_words": -1}, {"tile": 3}, {"precision": wmd.WMD_DIST_BF16}):
         with pytest.raises(wmd.WmdError) as e:
             wmd.Server(c, **kw)
         assert e.value.code == wmd.WMD_EINVAL, kw
