@@ -18,7 +18,8 @@
 //   v_i   = c_i / s_i                    (rows; every b holds a copy)
 //   x_k   = (1 / r_k) sum_i A[i][k] v_i  (partial over p, then summed over a)
 // Final: u = 1/x, v = c / (A u), WMD = sum_{i,k} ((K .* M)[i][k] u_k) v_i with
-// the products in FP32 and the sum in FP64, where K .* M is rebuilt from the
+// the products and each lane's sum over its (at most 8) columns of a row in
+// FP32 and the sum beyond in FP64, where K .* M is rebuilt from the
 // K block already in registers (M = n_i - ln K / lambda, n_i the row's
 // log-domain shift or 0) for lambda >= 0.5, else gathered from KMt; the
 // absolute error of the rebuilt M is about ulp(lambda M) / lambda, so its
@@ -126,13 +127,16 @@ __device__ __forceinline__ void sum_rows4(float& y0, float& y1, float& y2, float
     y3 = __uint_as_float(f[1]);
 }
 
-// ln k for a kernel value 0 < k <= 1 with the hardware log2 (inputs below
-// 2^-64 are scaled first, as the hardware op does not take denormals).  Its
-// absolute error (about 2^-22) enters M = n - ln(k) / lambda divided by lambda.
-__device__ __forceinline__ float ln_k(float k) {
-    const bool tiny = k < 0x1p-64f;
-    const float l2 = __builtin_amdgcn_logf(tiny ? k * 0x1p64f : k) - (tiny ? 64.f : 0.f);
-    return l2 * 0.693147180559945309f;
+// (K .* M) of a kernel value kk = exp(-lambda (M - n)): kk (n - ln(kk) / lambda),
+// with log2(kk) = exponent + log2(mantissa) (the hardware log2 flushes
+// denormal inputs; the mantissa is always normal, so denormal kk are exact),
+// and kk = 0 giving 0.  c = ln 2 / lambda.  The absolute error of the rebuilt
+// M is about ulp(lambda M) / lambda, so its relative error stays at FP32
+// rounding level.
+__device__ __forceinline__ float km_of(float kk, float n, float c) {
+    const float mant = fmaxf(__builtin_amdgcn_frexp_mantf(kk), 0.5f);
+    const float l2 = __builtin_amdgcn_logf(mant) + (float)__builtin_amdgcn_frexp_expf(kk);
+    return kk * fmaf(-l2, c, n);
 }
 
 // Lane-pair sums of two values at once over lane ^ 16 (ROW = 16) or lane ^ 32
@@ -235,12 +239,12 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
 #pragma unroll
             for (int q4 = 0; q4 < Q4; ++q4) {
                 const int k0 = kb + 4 * q4;
-                if (k0 < m) {
+                if (k0 < m) {   // columns m..ldk-1 of Kt hold zeros
                     const float4 t = *reinterpret_cast<const float4*>(rowp + k0);
                     A[p][4 * q4 + 0] = t.x;
-                    A[p][4 * q4 + 1] = (k0 + 1 < m) ? t.y : 0.f;
-                    A[p][4 * q4 + 2] = (k0 + 2 < m) ? t.z : 0.f;
-                    A[p][4 * q4 + 3] = (k0 + 3 < m) ? t.w : 0.f;
+                    A[p][4 * q4 + 1] = t.y;
+                    A[p][4 * q4 + 2] = t.z;
+                    A[p][4 * q4 + 3] = t.w;
                 }
             }
         }
@@ -386,23 +390,21 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
         }
     }
 
-    // WMD = sum_i v_i sum_k (K .* M)[i][k] u_k: FP32 products, FP64 sum.  K .* M
-    // is rebuilt from the K block in registers (M = n_i - ln K / lambda) or
+    // WMD = sum_i v_i sum_k (K .* M)[i][k] u_k: products and each lane's sum over
+    // its Q columns of a row in FP32, everything beyond in FP64.  K .* M is
+    // rebuilt from the K block in registers (M = n_i - ln K / lambda) or
     // gathered from KMt when lambda is too small for that.
     double wsum = 0.0;
     if (qp->km_from_k) {
-        const float il = qp->inv_lambda;
+        const float cl = 0.693147180559945309f * qp->inv_lambda;
 #pragma unroll
         for (int p = 0; p < PN; ++p) {
             const int i = a + R * p;
             const float nr = (qp->nrow && valid && i < n) ? qp->nrow[g.scol[rs + i]] : 0.f;
-            const double vp = (double)v[p];
+            float rsum = 0.f;
 #pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                const float kk = A[p][q];
-                const float km = (kk > 0.f) ? kk * (nr - ln_k(kk) * il) : 0.f;
-                wsum = fma((double)(km * u[q]), vp, wsum);
-            }
+            for (int q = 0; q < Q; ++q) rsum = fmaf(km_of(A[p][q], nr, cl), u[q], rsum);
+            wsum = fma((double)rsum, (double)v[p], wsum);
         }
     } else {
 #pragma unroll
@@ -410,19 +412,20 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
             const int i = a + R * p;
             if (valid && i < n) {
                 const float* row = qp->KMt + (int64_t)g.scol[rs + i] * ldk;
-                const double vp = (double)v[p];
+                float rsum = 0.f;
 #pragma unroll
                 for (int q4 = 0; q4 < Q4; ++q4) {
                     const int k0 = kb + 4 * q4;
                     if (k0 < m) {
                         float4 t = *reinterpret_cast<const float4*>(row + k0);
                         // u is zero beyond m, so the padded columns add nothing
-                        wsum = fma((double)(t.x * u[4 * q4 + 0]), vp, wsum);
-                        wsum = fma((double)(t.y * u[4 * q4 + 1]), vp, wsum);
-                        wsum = fma((double)(t.z * u[4 * q4 + 2]), vp, wsum);
-                        wsum = fma((double)(t.w * u[4 * q4 + 3]), vp, wsum);
+                        rsum = fmaf(t.x, u[4 * q4 + 0], rsum);
+                        rsum = fmaf(t.y, u[4 * q4 + 1], rsum);
+                        rsum = fmaf(t.z, u[4 * q4 + 2], rsum);
+                        rsum = fmaf(t.w, u[4 * q4 + 3], rsum);
                     }
                 }
+                wsum = fma((double)rsum, (double)v[p], wsum);
             }
         }
     }
@@ -595,20 +598,26 @@ __global__ __launch_bounds__(256) void k_sink_stream(SinkArgs g) {
             rho += fabs((double)u[k] * (double)acc - (double)qp->r[k]);
         }
     }
+    // per document word: FP32 sum over the query words in chunks of 8 (as the
+    // register tiles sum a lane's columns), FP64 beyond
     for (int i = tid; i < n; i += 256) {
         const int col = g.scol[rs + i];
         const double vi = (double)v[i];
         if (qp->km_from_k) {   // K .* M rebuilt from K: M = n_i - ln K / lambda
             const float* row = qp->Kt + (int64_t)col * ldk;
-            const float nr = qp->nrow ? qp->nrow[col] : 0.f, il = qp->inv_lambda;
-            for (int k = 0; k < m; ++k) {
-                const float kk = row[k];
-                const float km = (kk > 0.f) ? kk * (nr - ln_k(kk) * il) : 0.f;
-                wsum = fma((double)(km * u[k]), vi, wsum);
+            const float nr = qp->nrow ? qp->nrow[col] : 0.f, cl = 0.693147180559945309f * qp->inv_lambda;
+            for (int k0 = 0; k0 < m; k0 += 8) {
+                float rsum = 0.f;
+                for (int k = k0; k < min(k0 + 8, m); ++k) rsum = fmaf(km_of(row[k], nr, cl), u[k], rsum);
+                wsum = fma((double)rsum, vi, wsum);
             }
         } else {
             const float* row = qp->KMt + (int64_t)col * ldk;
-            for (int k = 0; k < m; ++k) wsum = fma((double)(row[k] * u[k]), vi, wsum);
+            for (int k0 = 0; k0 < m; k0 += 8) {
+                float rsum = 0.f;
+                for (int k = k0; k < min(k0 + 8, m); ++k) rsum = fmaf(row[k], u[k], rsum);
+                wsum = fma((double)rsum, vi, wsum);
+            }
         }
     }
     wsum = team_sum_f64<64>(wsum);
@@ -668,12 +677,12 @@ __global__ __launch_bounds__(64) void k_sink_rows(SinkArgs g) {
             const float* row = qp->Kt + (int64_t)g.scol[rs + i] * ldk;
 #pragma unroll
             for (int k4 = 0; k4 < MQ4; ++k4) {
-                if (4 * k4 < m) {
+                if (4 * k4 < m) {   // columns m..ldk-1 of Kt hold zeros
                     const float4 t = *reinterpret_cast<const float4*>(row + 4 * k4);
                     A[r][4 * k4 + 0] = t.x;
-                    A[r][4 * k4 + 1] = (4 * k4 + 1 < m) ? t.y : 0.f;
-                    A[r][4 * k4 + 2] = (4 * k4 + 2 < m) ? t.z : 0.f;
-                    A[r][4 * k4 + 3] = (4 * k4 + 3 < m) ? t.w : 0.f;
+                    A[r][4 * k4 + 1] = t.y;
+                    A[r][4 * k4 + 2] = t.z;
+                    A[r][4 * k4 + 3] = t.w;
                 }
             }
         }
@@ -745,8 +754,9 @@ __global__ __launch_bounds__(64) void k_sink_rows(SinkArgs g) {
         const float y = spmm();
         if (h == 0 && kv) rho = fabs((double)u * (double)y - (double)qp->r[kc]);
     }
-    // WMD = sum_i v_i sum_k (K .* M)[i][k] u_k: FP32 products, FP64 sum; K .* M
-    // rebuilt from the registers (M = n_i - ln K / lambda) or gathered from KMt
+    // WMD = sum_i v_i sum_k (K .* M)[i][k] u_k: products and sums over 8 query
+    // words in FP32, FP64 beyond; K .* M rebuilt from the registers
+    // (M = n_i - ln K / lambda) or gathered from KMt
     double wsum = 0.0;
 #pragma unroll
     for (int r = 0; r < RP; ++r) {
@@ -754,32 +764,34 @@ __global__ __launch_bounds__(64) void k_sink_rows(SinkArgs g) {
         if (i < n) {
             const double vr = (double)v[r];
             if (qp->km_from_k) {
-                const float il = qp->inv_lambda;
+                const float cl = 0.693147180559945309f * qp->inv_lambda;
                 const float nr = qp->nrow ? qp->nrow[g.scol[rs + i]] : 0.f;
 #pragma unroll
-                for (int k4 = 0; k4 < MQ4; ++k4) {
-                    const float4 uu = *reinterpret_cast<const float4*>(&uS[4 * k4]);
-                    const float ue[4] = {uu.x, uu.y, uu.z, uu.w};
+                for (int k8 = 0; k8 < MQ / 8; ++k8) {   // FP32 over 8 query words, FP64 beyond
+                    float rsum = 0.f;
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const float kk = A[r][4 * k4 + e];
-                        const float km = (kk > 0.f) ? kk * (nr - ln_k(kk) * il) : 0.f;
-                        wsum = fma((double)(km * ue[e]), vr, wsum);
-                    }
+                    for (int e = 0; e < 8; ++e) rsum = fmaf(km_of(A[r][8 * k8 + e], nr, cl), uS[8 * k8 + e], rsum);
+                    wsum = fma((double)rsum, vr, wsum);
                 }
             } else {
                 const float* row = qp->KMt + (int64_t)g.scol[rs + i] * ldk;
 #pragma unroll
-                for (int k4 = 0; k4 < MQ4; ++k4) {
-                    if (4 * k4 < m) {
-                        const float4 t = *reinterpret_cast<const float4*>(row + 4 * k4);
-                        const float4 uu = *reinterpret_cast<const float4*>(&uS[4 * k4]);
-                        // uS is zero past m, so the padded columns add nothing
-                        wsum = fma((double)(t.x * uu.x), vr, wsum);
-                        wsum = fma((double)(t.y * uu.y), vr, wsum);
-                        wsum = fma((double)(t.z * uu.z), vr, wsum);
-                        wsum = fma((double)(t.w * uu.w), vr, wsum);
+                for (int k8 = 0; k8 < MQ / 8; ++k8) {
+                    float rsum = 0.f;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int k4 = 2 * k8 + h;
+                        if (4 * k4 < m) {
+                            const float4 t = *reinterpret_cast<const float4*>(row + 4 * k4);
+                            const float4 uu = *reinterpret_cast<const float4*>(&uS[4 * k4]);
+                            // uS is zero past m, so the padded columns add nothing
+                            rsum = fmaf(t.x, uu.x, rsum);
+                            rsum = fmaf(t.y, uu.y, rsum);
+                            rsum = fmaf(t.z, uu.z, rsum);
+                            rsum = fmaf(t.w, uu.w, rsum);
+                        }
                     }
+                    wsum = fma((double)rsum, vr, wsum);
                 }
             }
         }
