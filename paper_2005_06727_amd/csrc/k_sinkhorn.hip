@@ -139,6 +139,25 @@ __device__ __forceinline__ float km_of(float kk, float n, float c) {
     return kk * fmaf(-l2, c, n);
 }
 
+// sum_q (K .* M)[q] u[q] over one row of Q kernel values (FP32): the plain
+// hardware log2 when every value of the row, in every lane of the wave, is a
+// normal number (the common case), else km_of for each value
+template <int Q>
+__device__ __forceinline__ float km_row(const float (&kk)[Q], const float (&u)[Q], float n, float c) {
+    float mn = kk[0];
+#pragma unroll
+    for (int q = 1; q < Q; ++q) mn = fminf(mn, kk[q]);
+    float rsum = 0.f;
+    if (__builtin_amdgcn_ballot_w64(!(mn >= 0x1p-126f)) == 0) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) rsum = fmaf(kk[q] * u[q], fmaf(-__builtin_amdgcn_logf(kk[q]), c, n), rsum);
+    } else {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) rsum = fmaf(km_of(kk[q], n, c), u[q], rsum);
+    }
+    return rsum;
+}
+
 // Lane-pair sums of two values at once over lane ^ 16 (ROW = 16) or lane ^ 32
 // (ROW = 32): a swap leaves one value's pair sum in each half, a second swap
 // copies both sums to both halves (each sum computed once, identical bits).
@@ -401,9 +420,7 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
         for (int p = 0; p < PN; ++p) {
             const int i = a + R * p;
             const float nr = (qp->nrow && valid && i < n) ? qp->nrow[g.scol[rs + i]] : 0.f;
-            float rsum = 0.f;
-#pragma unroll
-            for (int q = 0; q < Q; ++q) rsum = fmaf(km_of(A[p][q], nr, cl), u[q], rsum);
+            const float rsum = km_row<Q>(A[p], u, nr, cl);
             wsum = fma((double)rsum, (double)v[p], wsum);
         }
     } else {
