@@ -28,6 +28,13 @@
 // is c by construction).
 #include "wmd_internal.h"
 
+// No implicit multiply-add contraction in this file: every fused operation is
+// an explicit fmaf/fma.  The lane-exchange sums rely on both partners of a
+// butterfly adding the same two rounded values; a product contracted into the
+// exchange add (fma(a, b, partner) on one lane, fma(a', b', mine) on the other)
+// would give the copies different bits.
+#pragma clang fp contract(off)
+
 namespace wmd {
 
 namespace {
@@ -140,17 +147,24 @@ __device__ __forceinline__ float km_of(float kk, float n, float c) {
 }
 
 // sum_q (K .* M)[q] u[q] over one row of Q kernel values (FP32): the plain
-// hardware log2 when every value of the row, in every lane of the wave, is a
-// normal number (the common case), else km_of for each value
-template <int Q>
+// hardware log2 when no value of the row, in any lane of the team's part of
+// the wave, is a denormal (the common case; a zero gives a finite logarithm
+// of 2^-126 and so adds K = 0), else km_of for each value.  The choice
+// depends on the team's own document only (T < 64 masks the ballot to the
+// team's lanes), so a document's result does not depend on its neighbours.
+template <int Q, int T>
 __device__ __forceinline__ float km_row(const float (&kk)[Q], const float (&u)[Q], float n, float c) {
-    float mn = kk[0];
+    // bits - 1 as unsigned: +0 wraps to the maximum, denormals fall below 0x7fffff
+    uint32_t mn = __float_as_uint(kk[0]) - 1u;
 #pragma unroll
-    for (int q = 1; q < Q; ++q) mn = fminf(mn, kk[q]);
+    for (int q = 1; q < Q; ++q) mn = min(mn, __float_as_uint(kk[q]) - 1u);
+    uint64_t sub = __builtin_amdgcn_ballot_w64(mn < 0x7fffffu);
+    if constexpr (T < 64) sub &= ((1ull << T) - 1ull) << (__lane_id() & (64 - T));
     float rsum = 0.f;
-    if (__builtin_amdgcn_ballot_w64(!(mn >= 0x1p-126f)) == 0) {
+    if (sub == 0) {
 #pragma unroll
-        for (int q = 0; q < Q; ++q) rsum = fmaf(kk[q] * u[q], fmaf(-__builtin_amdgcn_logf(kk[q]), c, n), rsum);
+        for (int q = 0; q < Q; ++q)
+            rsum = fmaf(kk[q] * u[q], fmaf(-__builtin_amdgcn_logf(fmaxf(kk[q], 0x1p-126f)), c, n), rsum);
     } else {
 #pragma unroll
         for (int q = 0; q < Q; ++q) rsum = fmaf(km_of(kk[q], n, c), u[q], rsum);
@@ -226,9 +240,9 @@ __device__ __forceinline__ int wave_max(int v) {
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// One team's work on its document with PN rows per lane (PN a multiple of 4,
-// fixed at compile time so the code is straight-line; the kernel picks PN per
-// wave from the longest document of the wave).
+// One team's work on its document with PN rows per lane (fixed at compile
+// time so the code is straight-line; the kernel picks PN per wave from the
+// longest document of the wave).
 template <int R, int C, int P, int Q, int W, int PN>
 __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp, const bool valid, const int d,
                                           const int rs, const int n, const int m, const int ldk, const int a,
@@ -420,7 +434,7 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
         for (int p = 0; p < PN; ++p) {
             const int i = a + R * p;
             const float nr = (qp->nrow && valid && i < n) ? qp->nrow[g.scol[rs + i]] : 0.f;
-            const float rsum = km_row<Q>(A[p], u, nr, cl);
+            const float rsum = km_row<Q, T>(A[p], u, nr, cl);
             wsum = fma((double)rsum, (double)v[p], wsum);
         }
     } else {
@@ -467,6 +481,18 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
         const int doc = g.sdoc[d];
         qp->out[doc] = wsum;
         if (want_resid) qp->resid[doc] = rho;
+    }
+}
+
+// The smallest compiled PN (a multiple of STEP, at most P) that covers pr
+// rows per lane.  Results do not depend on PN: padded rows add exact zeros.
+template <int R, int C, int P, int Q, int W, int PN, int STEP, typename... Args>
+__device__ __forceinline__ void sink_dispatch(const int pr, Args&&... args) {
+    if constexpr (PN >= P) {
+        sink_team<R, C, P, Q, W, P>(args...);
+    } else {
+        if (pr <= PN) sink_team<R, C, P, Q, W, PN>(args...);
+        else sink_dispatch<R, C, P, Q, W, PN + STEP, STEP>(pr, args...);
     }
 }
 
@@ -519,24 +545,11 @@ __global__ __launch_bounds__(256) void k_sink(SinkArgs g) {
     }
     const int my_end = valid ? min(g.it_begin + g.it_count, qp->iters) : g.it_begin;
 
-    // rows per lane for this wave, in groups of 4 (documents of a launch are
-    // sorted by length, so the teams of a wave have similar n); uniform, SGPR
-    const int pg = __builtin_amdgcn_readfirstlane((wave_max((n + R - 1) / R) + 3) >> 2);
-#define WMD_SINK_TEAM(PN) \
-    sink_team<R, C, P, Q, W, PN>(g, qp, valid, d, rs, n, m, ldk, a, b, tl, wi, team, kb, it_end, my_end, s_part, s_red, \
-                                 s_rho)
-    if constexpr (P == 16) {
-        if (pg <= 1) WMD_SINK_TEAM(4);
-        else if (pg == 2) WMD_SINK_TEAM(8);
-        else if (pg == 3) WMD_SINK_TEAM(12);
-        else WMD_SINK_TEAM(16);
-    } else if constexpr (P == 8) {
-        if (pg <= 1) WMD_SINK_TEAM(4);
-        else WMD_SINK_TEAM(8);
-    } else {
-        WMD_SINK_TEAM(P);
-    }
-#undef WMD_SINK_TEAM
+    // rows per lane for this wave (documents of a launch are sorted by length,
+    // so the teams of a wave have similar n); uniform, SGPR
+    const int pr = __builtin_amdgcn_readfirstlane(wave_max((n + R - 1) / R));
+    sink_dispatch<R, C, P, Q, W, (P >= 16) ? 2 : 1, (P >= 16) ? 2 : 1>(
+        pr, g, qp, valid, d, rs, n, m, ldk, a, b, tl, wi, team, kb, it_end, my_end, s_part, s_red, s_rho);
 }
 
 // Any size: one 256-thread block per (query, document); the K block is
