@@ -490,6 +490,7 @@ int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wm
         a.scol = dc.scol;
         a.scw = dc.scw;
         a.sdoc = dc.sdoc;
+        a.zpad = dc.zpad;
         a.it_begin = it0;
         a.it_count = per_launch;
         a.final_step = (int64_t)it0 + per_launch >= max_iters ? 1 : 0;
@@ -563,6 +564,7 @@ static void corpus_free(wmd_corpus* c) {
     dfree(d.scol);
     dfree(d.scw);
     dfree(d.sdoc);
+    dfree(d.zpad);
     for (int sl = 0; sl < kWorkSlots; ++sl) free_workspace(c->ws[sl]);
     free_staging(c->stage);
     for (int i = 0; i < wmd_corpus::kTimingSlots; ++i)
@@ -685,13 +687,16 @@ int wmd_corpus_create(const float* vecs, int64_t V, int32_t dim, const int64_t* 
     if ((e = dalloc(&d.vecs, (size_t)V * ldv)) != hipSuccess || (e = dalloc(&d.act, (size_t)U * ldv)) != hipSuccess ||
         (e = dalloc(&d.act_norm, (size_t)U)) != hipSuccess || (e = dalloc(&d.act_word, (size_t)U)) != hipSuccess ||
         (e = dalloc(&d.sptr, (size_t)N + 1)) != hipSuccess || (e = dalloc(&d.scol, (size_t)nnz)) != hipSuccess ||
-        (e = dalloc(&d.scw, (size_t)nnz)) != hipSuccess || (e = dalloc(&d.sdoc, (size_t)N)) != hipSuccess)
+        (e = dalloc(&d.scw, (size_t)nnz)) != hipSuccess || (e = dalloc(&d.sdoc, (size_t)N)) != hipSuccess ||
+        (e = dalloc(&d.zpad, (size_t)kZpadFloats)) != hipSuccess)
         return bail(e, "corpus: device allocation");
     if (opt.bf16) {
         if ((e = dalloc(&d.act_bf16, (size_t)U * ldv)) != hipSuccess ||
             (e = dalloc(&d.act_norm_bf16, (size_t)U)) != hipSuccess)
             return bail(e, "corpus: BF16 allocation");
     }
+    std::vector<float> zpad((size_t)kZpadFloats, 0.f);
+    zpad[0] = 1.f;
     hipStream_t s = c->stream;
     if ((e = hipMemsetAsync(d.vecs, 0, (size_t)V * ldv * sizeof(float), s)) != hipSuccess ||
         (e = hipMemcpy2DAsync(d.vecs, ldv * sizeof(float), vecs, (size_t)dim * sizeof(float),
@@ -700,7 +705,8 @@ int wmd_corpus_create(const float* vecs, int64_t V, int32_t dim, const int64_t* 
         (e = hipMemcpyAsync(d.sptr, sptr.data(), sizeof(int32_t) * (N + 1), hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipMemcpyAsync(d.scol, scol.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipMemcpyAsync(d.scw, sw.data(), sizeof(float) * nnz, hipMemcpyHostToDevice, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(d.sdoc, order.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, s)) != hipSuccess)
+        (e = hipMemcpyAsync(d.sdoc, order.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(d.zpad, zpad.data(), sizeof(float) * kZpadFloats, hipMemcpyHostToDevice, s)) != hipSuccess)
         return bail(e, "corpus: upload");
     if ((e = launch_gather_rows(d.vecs, d.act_word, d.act, U, d.ldv, s)) != hipSuccess ||
         (e = launch_prep_norms(d.act, U, d.ldv, d.act_norm, s)) != hipSuccess ||
@@ -711,7 +717,7 @@ int wmd_corpus_create(const float* vecs, int64_t V, int32_t dim, const int64_t* 
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return bail(e, "corpus: preparation");
     c->device_bytes = (int64_t)((V + U) * ldv * sizeof(float) + U * (sizeof(float) + sizeof(int32_t)) +
                                 (N + 1 + N) * sizeof(int32_t) + nnz * (sizeof(int32_t) + sizeof(float)) +
-                                (opt.bf16 ? U * (ldv * sizeof(uint16_t) + sizeof(float)) : 0));
+                                kZpadFloats * sizeof(float) + (opt.bf16 ? U * (ldv * sizeof(uint16_t) + sizeof(float)) : 0));
     *out = c;
     return WMD_OK;
 }

@@ -26,6 +26,7 @@
 // relative error stays at FP32 rounding level.  Optionally the FP64 residual
 // sum_k |u_k (A^T v)_k - r_k| of the plan's row marginal (its column marginal
 // is c by construction).
+#include "wmd_device.h"
 #include "wmd_internal.h"
 
 // No implicit multiply-add contraction in this file: every fused operation is
@@ -257,51 +258,107 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
     // query has) and a padded column keeps x = 1: the reciprocals stay finite,
     // padded rows get v = 0 and padded columns add nothing, so the arithmetic
     // needs no per-element guards
-    float A[PN][Q];
+    const auto Kt = gmem(qp->Kt);
+    int col[PN];
     float cval[PN];
+    float A[PN][Q];
+    if constexpr (W == 1) {
+        // Branch-free loads, all in flight at once (a branch per row makes the
+        // compiler wait for each row's loads before issuing the next): the
+        // indices and weights of the lane's rows first, then the rows of Kt.
+        // A row beyond the document reads index 0 (present: every document has
+        // a word) and its Kt values from the zero block, whose first four
+        // values are (1, 0, 0, 0); a column group beyond m reads zeros there
+        // too.  Choosing the address instead of the loaded value keeps the
+        // loads' destinations in A (no second set of registers).
 #pragma unroll
-    for (int p = 0; p < PN; ++p) {
-        const int i = a + R * p;
-        const bool row = valid && i < n;
-        cval[p] = row ? g.scw[rs + i] : 0.f;
+        for (int p = 0; p < PN; ++p) {
+            const int i = a + R * p;
+            const int e = (valid && i < n) ? rs + i : 0;
+            col[p] = g.scol[e];
+            cval[p] = g.scw[e];
+        }
+        const auto zp = gmem(g.zpad);
 #pragma unroll
-        for (int q = 0; q < Q; ++q) A[p][q] = 0.f;
-        if (!row && kb == 0) A[p][0] = 1.f;
-        if (row) {
-            const float* rowp = qp->Kt + (int64_t)g.scol[rs + i] * ldk;
+        for (int p = 0; p < PN; ++p) {
+            const bool row = valid && a + R * p < n;
+            cval[p] = row ? cval[p] : 0.f;
 #pragma unroll
             for (int q4 = 0; q4 < Q4; ++q4) {
                 const int k0 = kb + 4 * q4;
-                if (k0 < m) {   // columns m..ldk-1 of Kt hold zeros
-                    const float4 t = *reinterpret_cast<const float4*>(rowp + k0);
-                    A[p][4 * q4 + 0] = t.x;
-                    A[p][4 * q4 + 1] = t.y;
-                    A[p][4 * q4 + 2] = t.z;
-                    A[p][4 * q4 + 3] = t.w;
+                const bool ld = row && k0 < m;   // columns m..ldk-1 of Kt hold zeros
+                const float4 t = ld4(ld ? Kt + (int64_t)col[p] * ldk + k0
+                                        : zp + ((!row && kb == 0 && q4 == 0) ? 0 : 4 + k0));
+                A[p][4 * q4 + 0] = t.x;
+                A[p][4 * q4 + 1] = t.y;
+                A[p][4 * q4 + 2] = t.z;
+                A[p][4 * q4 + 3] = t.w;
+            }
+        }
+    } else {
+        // Multi-wave teams (the largest A blocks) load row by row, which needs
+        // fewer registers; their rows' indices are read again where needed.
+#pragma unroll
+        for (int p = 0; p < PN; ++p) {
+            const int i = a + R * p;
+            const bool row = valid && i < n;
+            cval[p] = row ? g.scw[rs + i] : 0.f;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) A[p][q] = 0.f;
+            if (!row && kb == 0) A[p][0] = 1.f;
+            if (row) {
+                const auto rowp = Kt + (int64_t)g.scol[rs + i] * ldk;
+#pragma unroll
+                for (int q4 = 0; q4 < Q4; ++q4) {
+                    const int k0 = kb + 4 * q4;
+                    if (k0 < m) {   // columns m..ldk-1 of Kt hold zeros
+                        const float4 t = ld4(rowp + k0);
+                        A[p][4 * q4 + 0] = t.x;
+                        A[p][4 * q4 + 1] = t.y;
+                        A[p][4 * q4 + 2] = t.z;
+                        A[p][4 * q4 + 3] = t.w;
+                    }
                 }
             }
         }
     }
+    // the act row index of row p (valid rows only)
+    auto col_of = [&](int p) -> int {
+        if constexpr (W == 1) return col[p];
+        else return g.scol[rs + a + R * p];
+    };
 
-    float x[Q], rinv[Q], xpad[Q];
+    // per-column vectors, also branch-free; a column beyond m reads element 0
+    const auto rinvp = gmem(qp->rinv);
+    const auto rp = gmem(qp->r);
+    // convergence check (uniform over the launch: one tol per call)
+    const float tol = qp->tol;
+    const bool adaptive = tol > 0.f;
+    float x[Q], rinv[Q], xpad[Q], rq[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int k = kb + q;
         const bool kv = k < m;
-        rinv[q] = kv ? qp->rinv[k] : 0.f;
+        const int kc = kv ? k : 0;
+        const float ri = rinvp[kc];
+        const float rv = rp[kc];
+        rinv[q] = kv ? ri : 0.f;
+        rq[q] = (kv && adaptive) ? rv : 0.f;
         xpad[q] = kv ? 0.f : 1.f;
-        if (g.it_begin == 0) x[q] = kv ? 1.0f / (float)m : 1.f;
-        else x[q] = kv ? qp->x[(int64_t)d * ldk + k] : 1.f;
+        x[q] = kv ? 1.0f / (float)m : 1.f;
+    }
+    if (g.it_begin != 0) {
+        const auto xp = gmem(qp->x) + (int64_t)d * ldk;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const bool kv = kb + q < m;
+            const float xv = xp[kv ? kb + q : 0];
+            x[q] = kv ? xv : 1.f;
+        }
     }
 
     float u[Q], s[PN], v[PN], y[Q];
     int par = 0;
-    // convergence check (uniform over the launch: one tol per call)
-    const float tol = qp->tol;
-    const bool adaptive = tol > 0.f;
-    float rq[Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) rq[q] = (adaptive && kb + q < m) ? qp->r[kb + q] : 0.f;
     bool done = false;
     int t_done = g.it_begin;
 
@@ -396,13 +453,13 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
             }
         }
     }
-    if (g.final_step && qp->it_out && valid && tl == 0 && wi == 0) qp->it_out[g.sdoc[d]] = t_done;
+    if (g.final_step && qp->it_out && valid && tl == 0 && wi == 0) gmem(qp->it_out)[g.sdoc[d]] = t_done;
 
     if (!g.final_step) {
         if (valid && a == 0) {
 #pragma unroll
             for (int q = 0; q < Q; ++q)
-                if (kb + q < m) qp->x[(int64_t)d * ldk + kb + q] = x[q];
+                if (kb + q < m) gmem(qp->x)[(int64_t)d * ldk + kb + q] = x[q];
         }
         return;
     }
@@ -419,7 +476,7 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
         if (want_resid && a == 0) {
 #pragma unroll
             for (int q = 0; q < Q; ++q)
-                if (kb + q < m) rho += fabs((double)u[q] * (double)y[q] - (double)qp->r[kb + q]);
+                if (kb + q < m) rho += fabs((double)u[q] * (double)y[q] - (double)gmem(qp->r)[kb + q]);
         }
     }
 
@@ -433,31 +490,36 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
 #pragma unroll
         for (int p = 0; p < PN; ++p) {
             const int i = a + R * p;
-            const float nr = (qp->nrow && valid && i < n) ? qp->nrow[g.scol[rs + i]] : 0.f;
+            float nr = 0.f;
+            if (qp->nrow && valid && i < n) nr = gmem(qp->nrow)[col_of(p)];
             const float rsum = km_row<Q, T>(A[p], u, nr, cl);
             wsum = fma((double)rsum, (double)v[p], wsum);
         }
     } else {
+        const auto KMt = gmem(qp->KMt);
+        float4 t[PN][Q4];
 #pragma unroll
         for (int p = 0; p < PN; ++p) {
-            const int i = a + R * p;
-            if (valid && i < n) {
-                const float* row = qp->KMt + (int64_t)g.scol[rs + i] * ldk;
-                float rsum = 0.f;
+            const bool row = valid && a + R * p < n;
 #pragma unroll
-                for (int q4 = 0; q4 < Q4; ++q4) {
-                    const int k0 = kb + 4 * q4;
-                    if (k0 < m) {
-                        float4 t = *reinterpret_cast<const float4*>(row + k0);
-                        // u is zero beyond m, so the padded columns add nothing
-                        rsum = fmaf(t.x, u[4 * q4 + 0], rsum);
-                        rsum = fmaf(t.y, u[4 * q4 + 1], rsum);
-                        rsum = fmaf(t.z, u[4 * q4 + 2], rsum);
-                        rsum = fmaf(t.w, u[4 * q4 + 3], rsum);
-                    }
-                }
-                wsum = fma((double)rsum, (double)v[p], wsum);
+            for (int q4 = 0; q4 < Q4; ++q4) {
+                const int k0 = kb + 4 * q4;
+                const bool ld = row && k0 < m;
+                t[p][q4] = ld4(ld ? KMt + (int64_t)col_of(p) * ldk + k0 : gmem(g.zpad) + 4 + k0);
             }
+        }
+        // padded rows and columns add exact zeros (u is zero beyond m, v on padded rows)
+#pragma unroll
+        for (int p = 0; p < PN; ++p) {
+            float rsum = 0.f;
+#pragma unroll
+            for (int q4 = 0; q4 < Q4; ++q4) {
+                rsum = fmaf(t[p][q4].x, u[4 * q4 + 0], rsum);
+                rsum = fmaf(t[p][q4].y, u[4 * q4 + 1], rsum);
+                rsum = fmaf(t[p][q4].z, u[4 * q4 + 2], rsum);
+                rsum = fmaf(t[p][q4].w, u[4 * q4 + 3], rsum);
+            }
+            wsum = fma((double)rsum, (double)v[p], wsum);
         }
     }
     wsum = team_sum_f64<T>(wsum);
@@ -479,8 +541,8 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
     }
     if (valid && tl == 0 && wi == 0) {
         const int doc = g.sdoc[d];
-        qp->out[doc] = wsum;
-        if (want_resid) qp->resid[doc] = rho;
+        gmem(qp->out)[doc] = wsum;
+        if (want_resid) gmem(qp->resid)[doc] = rho;
     }
 }
 
@@ -497,11 +559,14 @@ __device__ __forceinline__ void sink_dispatch(const int pr, Args&&... args) {
 }
 
 template <int R, int C, int P, int Q, int W>
-__global__ __launch_bounds__(256) void k_sink(SinkArgs g) {
+// Occupancy targets: 3 waves per SIMD for 8 rows per lane, 2 for 16; the
+// multi-wave teams take what their registers allow.
+__global__ __launch_bounds__(256, (W > 1) ? 1 : (P >= 16) ? 2 : 3) void k_sink(SinkArgs g) {
     constexpr int T = R * C;
     static_assert(W == 1 || T == 64, "multi-wave teams use whole waves");
     static_assert(Q % 4 == 0, "columns are loaded as float4");
     static_assert(P % 4 == 0, "rows come in groups of 4");
+    static_assert(4 + C * Q * W <= kZpadFloats, "padded loads stay inside the zero block");
     constexpr int TPW = 64 / T;
     constexpr int TEAMS = (W == 1) ? 4 * TPW : 4 / W;
 
@@ -571,8 +636,8 @@ __global__ __launch_bounds__(256) void k_sink_stream(SinkArgs g) {
     float* ri = sh + 2 * m;
     float* v = sh + 3 * m;
     for (int k = tid; k < m; k += 256) {
-        ri[k] = qp->rinv[k];
-        x[k] = (g.it_begin == 0) ? 1.0f / (float)m : qp->x[(int64_t)d * ldk + k];
+        ri[k] = gmem(qp->rinv)[k];
+        x[k] = (g.it_begin == 0) ? 1.0f / (float)m : gmem(qp->x)[(int64_t)d * ldk + k];
     }
     __syncthreads();
     const int it_end = min(g.it_begin + g.it_count, qp->iters);
@@ -580,7 +645,7 @@ __global__ __launch_bounds__(256) void k_sink_stream(SinkArgs g) {
         for (int k = tid; k < m; k += 256) u[k] = rcp(x[k]);
         __syncthreads();
         for (int i = tid; i < n; i += 256) {
-            const float* row = qp->Kt + (int64_t)g.scol[rs + i] * ldk;
+            const auto row = gmem(qp->Kt) + (int64_t)g.scol[rs + i] * ldk;
             float acc = 0.f;
             for (int k = 0; k < m; ++k) acc = fmaf(row[k], u[k], acc);
             v[i] = g.scw[rs + i] * rcp(acc);
@@ -596,10 +661,10 @@ __global__ __launch_bounds__(256) void k_sink_stream(SinkArgs g) {
         for (int k = tid; k < m; k += 256) {
             float acc = 0.f;
             for (int i = 0; i < n; ++i)
-                acc = fmaf(qp->Kt[(int64_t)g.scol[rs + i] * ldk + k], v[i], acc);
+                acc = fmaf(gmem(qp->Kt)[(int64_t)g.scol[rs + i] * ldk + k], v[i], acc);
             const float xn = acc * ri[k];
             // convergence check: rho = sum_k r_k |x_new / x_old - 1|, u = 1 / x_old
-            if (tol > 0.f) rho = fmaf(qp->r[k], fabsf(xn * u[k] - 1.f), rho);
+            if (tol > 0.f) rho = fmaf(gmem(qp->r)[k], fabsf(xn * u[k] - 1.f), rho);
             x[k] = xn;
         }
         __syncthreads();
@@ -613,9 +678,9 @@ __global__ __launch_bounds__(256) void k_sink_stream(SinkArgs g) {
             if (tot <= tol) break;
         }
     }
-    if (g.final_step && qp->it_out && tid == 0) qp->it_out[g.sdoc[d]] = t_done;
+    if (g.final_step && qp->it_out && tid == 0) gmem(qp->it_out)[g.sdoc[d]] = t_done;
     if (!g.final_step) {
-        for (int k = tid; k < m; k += 256) qp->x[(int64_t)d * ldk + k] = x[k];
+        for (int k = tid; k < m; k += 256) gmem(qp->x)[(int64_t)d * ldk + k] = x[k];
         return;
     }
     sddmm();
@@ -624,8 +689,8 @@ __global__ __launch_bounds__(256) void k_sink_stream(SinkArgs g) {
         for (int k = tid; k < m; k += 256) {
             float acc = 0.f;
             for (int i = 0; i < n; ++i)
-                acc = fmaf(qp->Kt[(int64_t)g.scol[rs + i] * ldk + k], v[i], acc);
-            rho += fabs((double)u[k] * (double)acc - (double)qp->r[k]);
+                acc = fmaf(gmem(qp->Kt)[(int64_t)g.scol[rs + i] * ldk + k], v[i], acc);
+            rho += fabs((double)u[k] * (double)acc - (double)gmem(qp->r)[k]);
         }
     }
     // per document word: FP32 sum over the query words in chunks of 8 (as the
@@ -634,15 +699,15 @@ __global__ __launch_bounds__(256) void k_sink_stream(SinkArgs g) {
         const int col = g.scol[rs + i];
         const double vi = (double)v[i];
         if (qp->km_from_k) {   // K .* M rebuilt from K: M = n_i - ln K / lambda
-            const float* row = qp->Kt + (int64_t)col * ldk;
-            const float nr = qp->nrow ? qp->nrow[col] : 0.f, cl = 0.693147180559945309f * qp->inv_lambda;
+            const auto row = gmem(qp->Kt) + (int64_t)col * ldk;
+            const float nr = qp->nrow ? gmem(qp->nrow)[col] : 0.f, cl = 0.693147180559945309f * qp->inv_lambda;
             for (int k0 = 0; k0 < m; k0 += 8) {
                 float rsum = 0.f;
                 for (int k = k0; k < min(k0 + 8, m); ++k) rsum = fmaf(km_of(row[k], nr, cl), u[k], rsum);
                 wsum = fma((double)rsum, vi, wsum);
             }
         } else {
-            const float* row = qp->KMt + (int64_t)col * ldk;
+            const auto row = gmem(qp->KMt) + (int64_t)col * ldk;
             for (int k0 = 0; k0 < m; k0 += 8) {
                 float rsum = 0.f;
                 for (int k = k0; k < min(k0 + 8, m); ++k) rsum = fmaf(row[k], u[k], rsum);
@@ -659,8 +724,8 @@ __global__ __launch_bounds__(256) void k_sink_stream(SinkArgs g) {
     __syncthreads();
     if (tid == 0) {
         const int doc = g.sdoc[d];
-        qp->out[doc] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-        if (qp->resid) qp->resid[doc] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+        gmem(qp->out)[doc] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+        if (qp->resid) gmem(qp->resid)[doc] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
     }
 }
 
@@ -704,11 +769,11 @@ __global__ __launch_bounds__(64) void k_sink_rows(SinkArgs g) {
         for (int k = 0; k < MQ; ++k) A[r][k] = 0.f;
         if (i < n) {
             cval[r] = g.scw[rs + i];
-            const float* row = qp->Kt + (int64_t)g.scol[rs + i] * ldk;
+            const auto row = gmem(qp->Kt) + (int64_t)g.scol[rs + i] * ldk;
 #pragma unroll
             for (int k4 = 0; k4 < MQ4; ++k4) {
                 if (4 * k4 < m) {   // columns m..ldk-1 of Kt hold zeros
-                    const float4 t = *reinterpret_cast<const float4*>(row + 4 * k4);
+                    const float4 t = ld4(row + 4 * k4);
                     A[r][4 * k4 + 0] = t.x;
                     A[r][4 * k4 + 1] = t.y;
                     A[r][4 * k4 + 2] = t.z;
@@ -726,9 +791,9 @@ __global__ __launch_bounds__(64) void k_sink_rows(SinkArgs g) {
     const int n4 = (n + 3) & ~3;
     const int part = (((n4 / 4) + H - 1) / H) * 4;
     const int i0 = min(h * part, n4), i1 = min(i0 + part, n4);
-    const float rinv = kv ? qp->rinv[kc] : 0.f;
+    const float rinv = kv ? gmem(qp->rinv)[kc] : 0.f;
     float x = kv ? 1.0f / (float)m : 1.f;
-    if (g.it_begin > 0 && kv) x = qp->x[(int64_t)d * ldk + kc];
+    if (g.it_begin > 0 && kv) x = gmem(qp->x)[(int64_t)d * ldk + kc];
     float u = 0.f, v[RP];
 
     auto sddmm = [&](void) {
@@ -774,7 +839,7 @@ __global__ __launch_bounds__(64) void k_sink_rows(SinkArgs g) {
         x = spmm() * rinv;
     }
     if (!g.final_step) {
-        if (h == 0 && kv) qp->x[(int64_t)d * ldk + kc] = x;
+        if (h == 0 && kv) gmem(qp->x)[(int64_t)d * ldk + kc] = x;
         return;
     }
     u = kv ? rcp(x) : 0.f;
@@ -782,7 +847,7 @@ __global__ __launch_bounds__(64) void k_sink_rows(SinkArgs g) {
     double rho = 0.0;
     if (qp->resid) {
         const float y = spmm();
-        if (h == 0 && kv) rho = fabs((double)u * (double)y - (double)qp->r[kc]);
+        if (h == 0 && kv) rho = fabs((double)u * (double)y - (double)gmem(qp->r)[kc]);
     }
     // WMD = sum_i v_i sum_k (K .* M)[i][k] u_k: products and sums over 8 query
     // words in FP32, FP64 beyond; K .* M rebuilt from the registers
@@ -795,7 +860,7 @@ __global__ __launch_bounds__(64) void k_sink_rows(SinkArgs g) {
             const double vr = (double)v[r];
             if (qp->km_from_k) {
                 const float cl = 0.693147180559945309f * qp->inv_lambda;
-                const float nr = qp->nrow ? qp->nrow[g.scol[rs + i]] : 0.f;
+                const float nr = qp->nrow ? gmem(qp->nrow)[g.scol[rs + i]] : 0.f;
 #pragma unroll
                 for (int k8 = 0; k8 < MQ / 8; ++k8) {   // FP32 over 8 query words, FP64 beyond
                     float rsum = 0.f;
@@ -804,7 +869,7 @@ __global__ __launch_bounds__(64) void k_sink_rows(SinkArgs g) {
                     wsum = fma((double)rsum, vr, wsum);
                 }
             } else {
-                const float* row = qp->KMt + (int64_t)g.scol[rs + i] * ldk;
+                const auto row = gmem(qp->KMt) + (int64_t)g.scol[rs + i] * ldk;
 #pragma unroll
                 for (int k8 = 0; k8 < MQ / 8; ++k8) {
                     float rsum = 0.f;
@@ -812,7 +877,7 @@ __global__ __launch_bounds__(64) void k_sink_rows(SinkArgs g) {
                     for (int h = 0; h < 2; ++h) {
                         const int k4 = 2 * k8 + h;
                         if (4 * k4 < m) {
-                            const float4 t = *reinterpret_cast<const float4*>(row + 4 * k4);
+                            const float4 t = ld4(row + 4 * k4);
                             const float4 uu = *reinterpret_cast<const float4*>(&uS[4 * k4]);
                             // uS is zero past m, so the padded columns add nothing
                             rsum = fmaf(t.x, uu.x, rsum);
@@ -831,9 +896,9 @@ __global__ __launch_bounds__(64) void k_sink_rows(SinkArgs g) {
     (void)red;
     if (lane == 0) {
         const int doc = g.sdoc[d];
-        qp->out[doc] = wsum;
-        if (qp->resid) qp->resid[doc] = rho;
-        if (qp->it_out) qp->it_out[doc] = it_end;
+        gmem(qp->out)[doc] = wsum;
+        if (qp->resid) gmem(qp->resid)[doc] = rho;
+        if (qp->it_out) gmem(qp->it_out)[doc] = it_end;
     }
 }
 

@@ -53,7 +53,12 @@ struct DevCorpus {
     int32_t* scol = nullptr;        // nnz: act row index of each nonzero
     float* scw = nullptr;           // nnz: normalised weight c_ij
     int32_t* sdoc = nullptr;        // N: input id of each sorted document
+    float* zpad = nullptr;          // kZpadFloats: 1, 0, 0, ...: source of padding loads
 };
+
+// Floats in the corpus's padding block (1 followed by zeros), read by the
+// Sinkhorn kernels in place of the rows and columns beyond a document or query.
+constexpr int kZpadFloats = 1024;
 
 // Arguments of one fused Sinkhorn launch: every (query, document) pair with
 // query in qlist[0..nq) and document rank in [d_begin, d_end).
@@ -69,6 +74,7 @@ struct SinkArgs {
     int32_t it_begin;      // first iteration index handled by this launch
     int32_t it_count;      // iterations in this launch (clamped to each query's iters)
     int32_t final_step;    // nonzero: run the final u/v/WMD step at the end
+    const float* zpad;     // the corpus's zero block
 };
 
 // ---- launchers (return hipError_t of the launch) ----
