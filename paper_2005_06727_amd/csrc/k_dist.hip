@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <cstring>
 
+#include "wmd_device.h"
 #include "wmd_internal.h"
 
 namespace wmd {
@@ -353,12 +354,14 @@ struct NarrowArgs {
     int32_t qid_word;            // word index of the query ids in blob
     int32_t pwords;              // parameter block words
     uint32_t* params;            // device parameter block
+    const float* zpad;           // the corpus's zero block (1, then zeros)
     uint32_t blob[kUploadChunkBytes / 4];
 };
 
 template <bool BF16, int NC>
 __global__ __launch_bounds__(256) void k_dist_narrow(NarrowArgs a) {
     constexpr int SBB = NC * 128 + 16;   // LDS column stride (bytes): 8 lanes on distinct banks
+    static_assert(4 + 64 * NC <= kZpadFloats, "padded loads stay inside the zero block");
     __shared__ __attribute__((aligned(16))) char Bs[32 * SBB];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lg = lane >> 4;
@@ -368,48 +371,49 @@ __global__ __launch_bounds__(256) void k_dist_narrow(NarrowArgs a) {
     if (blockIdx.x == 0)
         for (int i = tid; i < a.pwords; i += 256) a.params[i] = a.blob[i];
 
-    // query columns -> LDS: 16-byte pieces, 32 columns x 8 NC pieces, NC per thread
-    {
-        uint4 v[NC];
+    // Every load is issued before the first wait, in three dependent rounds:
+    // the query ids (kernel arguments), then the query column pieces and the
+    // corpus rows.  Columns beyond m and rows beyond U read the zero block
+    // (the address is chosen, not the value, so nothing is selected later).
+    // Query columns -> LDS: 16-byte pieces, 32 columns x 8 NC pieces, NC per thread.
+    const auto zero = gmem(a.zpad) + 4;
+    int qrow[NC];
 #pragma unroll
-        for (int j = 0; j < NC; ++j) {
-            const int p = tid + 256 * j;
-            const int cl = p / (8 * NC), seg = p % (8 * NC);
-            v[j] = make_uint4(0u, 0u, 0u, 0u);
-            if (cl < m) {
-                const float* src = a.vecs + (int64_t)(int32_t)a.blob[a.qid_word + cl] * ldv;
-                if constexpr (BF16) {
-                    const float4 f0 = reinterpret_cast<const float4*>(src + seg * 8)[0];
-                    const float4 f1 = reinterpret_cast<const float4*>(src + seg * 8)[1];
-                    v[j].x = bf16_rne(f0.x) | ((uint32_t)bf16_rne(f0.y) << 16);
-                    v[j].y = bf16_rne(f0.z) | ((uint32_t)bf16_rne(f0.w) << 16);
-                    v[j].z = bf16_rne(f1.x) | ((uint32_t)bf16_rne(f1.y) << 16);
-                    v[j].w = bf16_rne(f1.z) | ((uint32_t)bf16_rne(f1.w) << 16);
-                } else {
-                    v[j] = *reinterpret_cast<const uint4*>(src + seg * 4);
-                }
-            }
-        }
+    for (int j = 0; j < NC; ++j) {
+        const int cl = (tid + 256 * j) / (8 * NC);
+        qrow[j] = (int32_t)a.blob[a.qid_word + (cl < m ? cl : 0)];
+    }
+    uint4 v[NC];
 #pragma unroll
-        for (int j = 0; j < NC; ++j) {
-            const int p = tid + 256 * j;
-            *reinterpret_cast<uint4*>(&Bs[(p / (8 * NC)) * SBB + (p % (8 * NC)) * 16]) = v[j];
+    for (int j = 0; j < NC; ++j) {
+        const int p = tid + 256 * j;
+        const int cl = p / (8 * NC), seg = p % (8 * NC);
+        const auto src = (cl < m) ? gmem(a.vecs) + (int64_t)qrow[j] * ldv : zero;
+        if constexpr (BF16) {
+            const float4 f0 = ld4(src + seg * 8);
+            const float4 f1 = ld4(src + seg * 8 + 4);
+            v[j].x = bf16_rne(f0.x) | ((uint32_t)bf16_rne(f0.y) << 16);
+            v[j].y = bf16_rne(f0.z) | ((uint32_t)bf16_rne(f0.w) << 16);
+            v[j].z = bf16_rne(f1.x) | ((uint32_t)bf16_rne(f1.y) << 16);
+            v[j].w = bf16_rne(f1.z) | ((uint32_t)bf16_rne(f1.w) << 16);
+        } else {
+            const float4 f = ld4(src + seg * 4);
+            v[j] = make_uint4(__float_as_uint(f.x), __float_as_uint(f.y), __float_as_uint(f.z), __float_as_uint(f.w));
         }
     }
     uint4 fa[NC][2];
     {
         const int64_t row = rbase + lr;
-        if (row < a.U) {
-            const char* src = BF16 ? reinterpret_cast<const char*>(a.act16 + row * ldv)
-                                   : reinterpret_cast<const char*>(a.act + row * ldv);
+        const char* src = (row >= a.U) ? reinterpret_cast<const char*>(a.zpad + 4)
+                          : BF16       ? reinterpret_cast<const char*>(a.act16 + row * ldv)
+                                       : reinterpret_cast<const char*>(a.act + row * ldv);
+        const auto gs = gmem(src);
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                fa[c][0] = *reinterpret_cast<const uint4*>(src + c * 128 + lg * 32);
-                fa[c][1] = *reinterpret_cast<const uint4*>(src + c * 128 + lg * 32 + 16);
-            }
-        } else {
-#pragma unroll
-            for (int c = 0; c < NC; ++c) fa[c][0] = fa[c][1] = make_uint4(0u, 0u, 0u, 0u);
+        for (int c = 0; c < NC; ++c) {
+            const float4 f0 = ld4(reinterpret_cast<WMD_GLOBAL const float*>(gs + c * 128 + lg * 32));
+            const float4 f1 = ld4(reinterpret_cast<WMD_GLOBAL const float*>(gs + c * 128 + lg * 32 + 16));
+            fa[c][0] = make_uint4(__float_as_uint(f0.x), __float_as_uint(f0.y), __float_as_uint(f0.z), __float_as_uint(f0.w));
+            fa[c][1] = make_uint4(__float_as_uint(f1.x), __float_as_uint(f1.y), __float_as_uint(f1.z), __float_as_uint(f1.w));
         }
     }
     int e_word[4];
@@ -417,8 +421,16 @@ __global__ __launch_bounds__(256) void k_dist_narrow(NarrowArgs a) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int64_t gi = rbase + 4 * lg + r;
-        e_word[r] = (gi < a.U) ? a.act_word[gi] : -2;
-        e_norm[r] = (gi < a.U) ? a.norm[gi] : 0.f;
+        const int64_t gc = (gi < a.U) ? gi : 0;
+        const int w = a.act_word[gc];
+        const float nv = a.norm[gc];
+        e_word[r] = (gi < a.U) ? w : -2;
+        e_norm[r] = (gi < a.U) ? nv : 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+        const int p = tid + 256 * j;
+        *reinterpret_cast<uint4*>(&Bs[(p / (8 * NC)) * SBB + (p % (8 * NC)) * 16]) = v[j];
     }
     int qw[2];
 #pragma unroll
@@ -604,6 +616,7 @@ hipError_t launch_dist_narrow(const DevCorpus& c, const QueryDev& hq, const Quer
     a.qid_word = (int32_t)(off_id / 4);
     a.pwords = (int32_t)(pbytes / 4);
     a.params = static_cast<uint32_t*>(params_dev);
+    a.zpad = c.zpad;
     std::memset(a.blob, 0, sizeof a.blob);
     std::memcpy(a.blob, blob, pbytes);
     hipError_t e;
