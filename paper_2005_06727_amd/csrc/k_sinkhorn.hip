@@ -241,6 +241,9 @@ __device__ __forceinline__ int wave_max(int v) {
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// added to every x update (see sink_team)
+constexpr float kXPad = 0x1p-126f;
+
 // One team's work on its document with PN rows per lane (fixed at compile
 // time so the code is straight-line; the kernel picks PN per wave from the
 // longest document of the wave).
@@ -255,10 +258,13 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
 
     // A and every per-row / per-column vector are zero outside the document's
     // n x m block, except that a padded row holds 1 in column 0 (which every
-    // query has) and a padded column keeps x = 1: the reciprocals stay finite,
-    // padded rows get v = 0 and padded columns add nothing, so the arithmetic
-    // needs no per-element guards
+    // query has) and x on a padded column is 2^-126: the update adds 2^-126
+    // to y / r (which leaves every x >= 2^-102 unchanged, and is all of x where
+    // y and 1/r are zero), so the reciprocals stay finite, padded rows get
+    // v = 0 and padded columns add exact zeros; the arithmetic needs no
+    // per-element guards and no per-column padding register.
     const auto Kt = gmem(qp->Kt);
+    const int doc = g.sdoc[d];   // output slot, loaded with the indices
     int col[PN];
     float cval[PN];
     float A[PN][Q];
@@ -334,7 +340,7 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
     // convergence check (uniform over the launch: one tol per call)
     const float tol = qp->tol;
     const bool adaptive = tol > 0.f;
-    float x[Q], rinv[Q], xpad[Q], rq[Q];
+    float x[Q], rinv[Q], rq[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int k = kb + q;
@@ -344,7 +350,6 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
         const float rv = rp[kc];
         rinv[q] = kv ? ri : 0.f;
         rq[q] = (kv && adaptive) ? rv : 0.f;
-        xpad[q] = kv ? 0.f : 1.f;
         x[q] = kv ? 1.0f / (float)m : 1.f;
     }
     if (g.it_begin != 0) {
@@ -426,7 +431,7 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
             // (same barriers); a team past its own count computes but keeps x
             if (W == 1 || it < my_end) {
 #pragma unroll
-                for (int q = 0; q < Q; ++q) x[q] = fmaf(y[q], rinv[q], xpad[q]);
+                for (int q = 0; q < Q; ++q) x[q] = fmaf(y[q], rinv[q], kXPad);
                 t_done = it + 1;
             }
         } else {
@@ -435,7 +440,7 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
             float rho = 0.f;
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
-                xn[q] = fmaf(y[q], rinv[q], xpad[q]);
+                xn[q] = fmaf(y[q], rinv[q], kXPad);
                 rho = fmaf(rq[q], fabsf(xn[q] * u[q] - 1.f), rho);
             }
             sum_over_b_n<C, 1>(&rho);
@@ -453,7 +458,7 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
             }
         }
     }
-    if (g.final_step && qp->it_out && valid && tl == 0 && wi == 0) gmem(qp->it_out)[g.sdoc[d]] = t_done;
+    if (g.final_step && qp->it_out && valid && tl == 0 && wi == 0) gmem(qp->it_out)[doc] = t_done;
 
     if (!g.final_step) {
         if (valid && a == 0) {
@@ -464,9 +469,9 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
         return;
     }
 
-    // final step: u = 1/x (0 on padded columns), v = c / (K^T u)
+    // final step: u = 1/x (finite on padded columns, where A is zero), v = c / (K^T u)
 #pragma unroll
-    for (int q = 0; q < Q; ++q) u[q] = (xpad[q] == 0.f) ? rcp(x[q]) : 0.f;
+    for (int q = 0; q < Q; ++q) u[q] = rcp(x[q]);
     sddmm();
 
     double rho = 0.0;
@@ -487,12 +492,20 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
     double wsum = 0.0;
     if (qp->km_from_k) {
         const float cl = 0.693147180559945309f * qp->inv_lambda;
+        // the rows' log-domain shifts, loaded together (the pointer is uniform)
+        float nr[PN];
+        const auto nrowp = gmem(qp->nrow);
+        if (nrowp) {
+            const auto zp = gmem(g.zpad) + 4;
+#pragma unroll
+            for (int p = 0; p < PN; ++p) nr[p] = *((valid && a + R * p < n) ? nrowp + col_of(p) : zp);
+        } else {
+#pragma unroll
+            for (int p = 0; p < PN; ++p) nr[p] = 0.f;
+        }
 #pragma unroll
         for (int p = 0; p < PN; ++p) {
-            const int i = a + R * p;
-            float nr = 0.f;
-            if (qp->nrow && valid && i < n) nr = gmem(qp->nrow)[col_of(p)];
-            const float rsum = km_row<Q, T>(A[p], u, nr, cl);
+            const float rsum = km_row<Q, T>(A[p], u, nr[p], cl);
             wsum = fma((double)rsum, (double)v[p], wsum);
         }
     } else {
@@ -540,7 +553,6 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
         }
     }
     if (valid && tl == 0 && wi == 0) {
-        const int doc = g.sdoc[d];
         gmem(qp->out)[doc] = wsum;
         if (want_resid) gmem(qp->resid)[doc] = rho;
     }
@@ -558,9 +570,9 @@ __device__ __forceinline__ void sink_dispatch(const int pr, Args&&... args) {
     }
 }
 
-template <int R, int C, int P, int Q, int W>
 // Occupancy targets: 3 waves per SIMD for 8 rows per lane, 2 for 16; the
 // multi-wave teams take what their registers allow.
+template <int R, int C, int P, int Q, int W>
 __global__ __launch_bounds__(256, (W > 1) ? 1 : (P >= 16) ? 2 : 3) void k_sink(SinkArgs g) {
     constexpr int T = R * C;
     static_assert(W == 1 || T == 64, "multi-wave teams use whole waves");
@@ -581,14 +593,16 @@ __global__ __launch_bounds__(256, (W > 1) ? 1 : (P >= 16) ? 2 : 3) void k_sink(S
     const int wi = (W == 1) ? 0 : wave % W;
     const int a = tl / C, b = tl % C;
 
-    const int64_t item = (int64_t)blockIdx.x * TEAMS + team;
+    // Each query's documents fill whole blocks (the launch pads them to a
+    // multiple of TEAMS), so the query, and every field of its record, is
+    // uniform over the block: the compiler reads them with scalar loads.
     const int nd = g.d_end - g.d_begin;
-    const bool valid = item < (int64_t)g.nq * nd;
-    int qidx = 0, d = g.d_begin;
-    if (valid) {
-        qidx = g.qlist[item / nd];
-        d = g.d_begin + (int)(item % nd);
-    }
+    const int bpq = (nd + TEAMS - 1) / TEAMS;   // blocks per query
+    const int qi = (int)(blockIdx.x / bpq);
+    const int dd = (int)(blockIdx.x % bpq) * TEAMS + team;
+    const bool valid = qi < g.nq && dd < nd;
+    const int qidx = g.qlist[qi < g.nq ? qi : 0];
+    const int d = g.d_begin + (valid ? dd : 0);
     const QueryDev* qp = g.qd + qidx;
     const int m = valid ? qp->m : 0;
     const int ldk = qp->ldk;
@@ -969,7 +983,9 @@ hipError_t launch_sinkhorn(int shape, const SinkArgs& a, int max_m, int max_n, h
         return hipGetLastError();
     }
     const Shape& sh = kShapes[shape];
-    const int64_t blocks = (nitems + sh.teams_per_block - 1) / sh.teams_per_block;
+    // register tiles: each query's documents padded to whole blocks; the row
+    // kernel has one team per block, so this is nitems for it
+    const int64_t blocks = (int64_t)a.nq * ((a.d_end - a.d_begin + sh.teams_per_block - 1) / sh.teams_per_block);
     hipLaunchKernelGGL(sh.kern, dim3((unsigned)blocks), dim3(sh.threads), 0, s, a);
     return hipGetLastError();
 }
