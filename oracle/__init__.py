@@ -9,3 +9,4 @@ from .sinkhorn_wmd import (  # noqa: F401
     sinkhorn_wmd_dense, sinkhorn_wmd_sparse,
 )
 from .retrieval import knn  # noqa: F401
+from .sinkhorn_lse import sinkhorn_wmd_lse, sinkhorn_lse_core  # noqa: F401
