@@ -77,13 +77,26 @@ typedef struct wmd_query_options {
                                  between calls with the same tile, and agree across
                                  tiles to FP32 rounding. */
     float   tol;              /* 0: exactly `iters` x updates per document (default).
-                                 > 0: the convergence check of Algorithm 1 ("while x
-                                 changes"): after each x update a document stops once
+                                 > 0: the convergence check of Algorithm 1 (iterate
+                                 while x still changes): after each x update a document stops once
                                  rho = sum_k r_k |x_k(t) / x_k(t-1) - 1| <= tol (rho is
                                  the row-marginal residual of the plan built from
                                  x(t-1)), else after `iters` updates.  The decision is
                                  taken in FP32.  Needs iters_per_launch = 0 and a tile
                                  of -1, -2 or 0..7. */
+    int32_t lse;              /* nonzero: the same iteration carried in the log domain
+                                 (Algorithm 1 on log u and log v, every product with K
+                                 evaluated as a log-sum-exp over the same nonzeros, Sec. 4),
+                                 for lambda beyond the range of K = exp(-lambda M) even
+                                 with the column shift.  Distances are computed in FP64 as
+                                 direct differences, the potentials are FP64 and only the
+                                 exponentials of non-positive arguments are FP32, so the
+                                 FP32 accuracy bar holds at any lambda.  Needs precision
+                                 WMD_DIST_FP32, tol = 0, iters_per_launch = 0, tile = -1
+                                 and log_domain = 0 (WMD_EINVAL otherwise).  Limits:
+                                 32 * (embedding row + 4) floats and 16 (v_r + longest
+                                 document) + 4 (longest document) bytes of LDS, each at
+                                 most 160 KB (WMD_EINVAL beyond). */
 } wmd_query_options;
 
 typedef struct wmd_corpus_info {

@@ -112,6 +112,10 @@ int check_query_options(const wmd_query_options* in, wmd_query_options* o) {
         return fail(WMD_EINVAL, "options: the convergence check (tol > 0) needs iters_per_launch = 0");
     if (o->tol > 0.f && o->tile >= 0 && !sinkhorn_shape_adaptive(o->tile))
         return fail(WMD_EINVAL, "options: tile %d has no convergence check", o->tile);
+    if (o->lse && (o->precision != WMD_DIST_FP32 || o->tol > 0.f || o->iters_per_launch > 0 || o->tile != -1 ||
+                   o->log_domain))
+        return fail(WMD_EINVAL, "options: lse needs FP32 precision, tol = 0, iters_per_launch = 0, tile = -1 "
+                                "and log_domain = 0");
     return WMD_OK;
 }
 
@@ -172,8 +176,8 @@ Layout make_layout(const wmd_corpus* c, const std::vector<PlannedQuery>& qs, con
     }
     L.per_launch = opt.iters_per_launch > 0 ? opt.iters_per_launch : INT_MAX;
     L.chunked = L.per_launch < L.max_iters;
-    L.kfloats = (size_t)U * L.sum_ldk;
-    L.kmfloats = any_km ? L.kfloats : 0;
+    L.kfloats = (size_t)U * L.sum_ldk * (opt.lse ? 2 : 1);   // the log-domain form keeps FP64 distances
+    L.kmfloats = (any_km && !opt.lse) ? L.kfloats : 0;
     L.xfloats = L.chunked ? (size_t)N * L.sum_ldk : 0;
     L.nfloats = opt.log_domain ? (size_t)U * B : 0;
     // parameter block: QueryDev[B] | qlist[B] | kofs[B+1] | qid[sum_m] | r[sum_m] | rinv[sum_m]
@@ -368,6 +372,9 @@ int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wm
     (void)max_iters;
     if (opt.tile >= 0 && !sinkhorn_shape_fits(opt.tile, max_m, 1))
         return fail(WMD_EINVAL, "options: tile %d cannot hold a %d-word query", opt.tile, max_m);
+    if (opt.lse && (lse_dist_lds_bytes(dc.ldv) > kLseMaxLds || lse_sink_lds_bytes(max_m, dc.max_doc) > kLseMaxLds))
+        return fail(WMD_EINVAL, "options: lse: a %d-word query against %d-word documents (dimension %d) exceeds "
+                                "the local memory of one workgroup", max_m, dc.max_doc, dc.dim);
     int rc = ensure_workspace(w, L, need_host_out);
     if (rc) return rc;
     int32_t* dev_iters = nullptr;
@@ -406,7 +413,7 @@ int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wm
         d.qid = reinterpret_cast<const int32_t*>(dp + off_id) + mo;
         d.r = reinterpret_cast<const float*>(dp + off_r) + mo;
         d.rinv = reinterpret_cast<const float*>(dp + off_ri) + mo;
-        d.Kt = w.Kt + (size_t)U * ko;
+        d.Kt = w.Kt + (size_t)U * ko * (opt.lse ? 2 : 1);   // log domain: U x ldk doubles per query
         d.KMt = L.kmfloats ? w.KMt + (size_t)U * ko : nullptr;
         d.x = chunked ? w.x + (size_t)N * ko : nullptr;
         d.out = dev_out + (size_t)b * N;
@@ -454,7 +461,7 @@ int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wm
         return hip_fail(e, "query: order after the slot's previous call");
     // one short query: its parameters ride along with the distance kernel
     const int bf16 = opt.precision == WMD_DIST_BF16 ? 1 : 0;
-    const bool narrow = by_args && dist_narrow_fits(dc, bf16, B, (int)sum_ldk, pbytes);
+    const bool narrow = !opt.lse && by_args && dist_narrow_fits(dc, bf16, B, (int)sum_ldk, pbytes);
     if (by_args) {
         if (!narrow && (e = launch_upload(hp, pbytes, dp, stream)) != hipSuccess)
             return hip_fail(e, "query: upload parameters");
@@ -476,14 +483,34 @@ int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wm
         (void)hipEventRecord(c->ev[slot][0], stream);
     }
     const int32_t* dqg = reinterpret_cast<const int32_t*>(dp + off_qg);
-    if (narrow) e = launch_dist_narrow(dc, hq[0], dq, hp, pbytes, off_id, dp, bf16, stream);
+    if (opt.lse) e = launch_dist_lse(dc, dq, dqg, B, (int)sum_ldk, stream);
+    else if (narrow) e = launch_dist_narrow(dc, hq[0], dq, hp, pbytes, off_id, dp, bf16, stream);
     else e = launch_dist(dc, dq, dqg, B, (int)sum_ldk, bf16, opt.log_domain, w.nrow, stream);
     if (e != hipSuccess) return hip_fail(e, "query: distance kernel launch");
     ++launches;
     if (slot >= 0) (void)hipEventRecord(c->ev[slot][1], stream);
 
     const int d_tile = (int)c->d_tile;   // sorted docs [d_tile, N) fit the register tiles
-    for (int it0 = 0;; it0 += per_launch) {
+    if (opt.lse) {   // every query and document in one log-domain launch
+        SinkArgs a;
+        a.qd = dq;
+        a.qlist = dql;
+        a.nq = B;
+        a.d_begin = 0;
+        a.d_end = (int)N;
+        a.sptr = dc.sptr;
+        a.scol = dc.scol;
+        a.scw = dc.scw;
+        a.sdoc = dc.sdoc;
+        a.zpad = dc.zpad;
+        a.it_begin = 0;
+        a.it_count = max_iters;
+        a.final_step = 1;
+        if ((e = launch_sinkhorn_lse(a, max_m, dc.max_doc, stream)) != hipSuccess)
+            return hip_fail(e, "query: log-domain sinkhorn launch");
+        ++launches;
+    }
+    for (int it0 = 0; !opt.lse; it0 += per_launch) {
         SinkArgs a;
         a.qd = dq;
         a.sptr = dc.sptr;
@@ -550,6 +577,7 @@ void wmd_query_options_init(wmd_query_options* opt) {
     opt->iters_per_launch = 0;
     opt->tile = -1;
     opt->tol = 0.f;
+    opt->lse = 0;
 }
 
 static void corpus_free(wmd_corpus* c) {

@@ -1,0 +1,267 @@
+// The Sinkhorn iteration of Algorithm 1 carried in the log domain, for lambda
+// beyond the range of K = exp(-lambda M) (FP32: lambda M > ~87, FP64: > ~745).
+//
+// With lu = log u, lv = log v and log K = -lambda M, the iteration of the
+// sparse form (Sec. 4) becomes, per document:
+//   lv_i = log c_i - LSE_k(lu_k - lambda M[k, i])         (SDDMM at the nonzeros)
+//   lu_k = log r_k - LSE_i(lv_i - lambda M[k, i])         (SpMM, then u = 1/x)
+// with LSE_j(a_j) = max_j a + log sum_j exp(a_j - max_j a), and x = 1/v_r at
+// the start (lu = log v_r).  The final step needs no large exponent at all:
+// with w_ik = exp(lu_k - lambda M[k, i] - max_k(...)) the document's share of
+// row i is v_i sum_k u_k K_ki M_ki = c_i (sum_k w_ik M_ki) / (sum_k w_ik).
+//
+// Precision: the distances are FP64 (direct differences of the FP32 rows, as
+// the definition writes them), the potentials lu, lv, the exponent arguments
+// and the maxima are FP64; only exp(a - max) (a non-positive argument, so the
+// terms that matter have small magnitude) and the sums of those terms are
+// FP32.  FP32 distances would not do: lambda times their rounding error is
+// already ~1e-4 at lambda = 1000.
+#include "wmd_device.h"
+#include "wmd_internal.h"
+
+namespace wmd {
+
+namespace {
+
+constexpr int kRows = 8;       // corpus rows per distance block
+constexpr int kCols = 32;      // query columns per distance block
+constexpr double kLog2e = 1.4426950408889634;
+
+struct LseDistArgs {
+    const float* act;          // U x ldv FP32 corpus rows (zero padded)
+    const float* vecs;         // V x ldv FP32 vocabulary rows (zero padded)
+    const QueryDev* qd;        // B queries; Kt of each holds U x ldk doubles here
+    const int32_t* kofs;       // B + 1: first global column of each query
+    int64_t U;
+    int32_t ldv;
+    int32_t B;
+    int32_t ncols;             // kofs[B]
+};
+
+// the query of global column c: the largest b with kofs[b] <= c
+__device__ int query_of_col(const int32_t* kofs, int B, int c) {
+    int lo = 0, hi = B - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (kofs[mid] <= c) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// d[i, c] = sqrt(sum_d (E[word(i), d] - E[qid(c), d])^2) in FP64 for 8 corpus
+// rows x 32 global query columns per block; thread (row rl, column cl).  The
+// 32 query rows are staged in LDS (FP32, row stride ldv + 4).  Columns
+// m_b <= k < ldk_b are written as zeros.
+__global__ __launch_bounds__(256) void k_dist_lse(LseDistArgs a) {
+    extern __shared__ float4 qsh4[];
+    float* qsh = reinterpret_cast<float*>(qsh4);
+    __shared__ int64_t qrow[kCols];     // vocabulary row of each column, -1 for padding
+    __shared__ int qb[kCols], qk[kCols];
+    const int tid = threadIdx.x;
+    const int cl = tid % kCols, rl = tid / kCols;
+    const int c0 = blockIdx.y * kCols;
+    const int stride = a.ldv + 4;
+    if (tid < kCols) {
+        const int c = c0 + tid;
+        int64_t row = -1;
+        int b = 0, k = 0;
+        if (c < a.ncols) {
+            b = query_of_col(a.kofs, a.B, c);
+            k = c - a.kofs[b];
+            if (k < a.qd[b].m) row = a.qd[b].qid[k];
+        }
+        qrow[tid] = row;
+        qb[tid] = b;
+        qk[tid] = k;
+    }
+    __syncthreads();
+    const int q4 = a.ldv / 4;
+    for (int p = tid; p < kCols * q4; p += 256) {
+        const int cc = p / q4, e = p % q4;
+        const int64_t row = qrow[cc];
+        const float4 v = row >= 0 ? ld4(gmem(a.vecs) + row * a.ldv + 4 * e) : make_float4(0.f, 0.f, 0.f, 0.f);
+        *reinterpret_cast<float4*>(qsh + cc * stride + 4 * e) = v;
+    }
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * kRows + rl;
+    const int c = c0 + cl;
+    const auto arow = gmem(a.act) + (i < a.U ? i : 0) * a.ldv;
+    const float* brow = qsh + cl * stride;
+    double acc = 0.0;
+    for (int e = 0; e < q4; ++e) {
+        const float4 x = ld4(arow + 4 * e);
+        const float4 y = *reinterpret_cast<const float4*>(brow + 4 * e);
+        const double d0 = (double)x.x - (double)y.x, d1 = (double)x.y - (double)y.y;
+        const double d2 = (double)x.z - (double)y.z, d3 = (double)x.w - (double)y.w;
+        acc = fma(d0, d0, acc);
+        acc = fma(d1, d1, acc);
+        acc = fma(d2, d2, acc);
+        acc = fma(d3, d3, acc);
+    }
+    if (i < a.U && c < a.ncols) {
+        const QueryDev& q = a.qd[qb[cl]];
+        double* D = reinterpret_cast<double*>(q.Kt);
+        gmem(D)[i * q.ldk + qk[cl]] = qrow[cl] >= 0 ? sqrt(acc) : 0.0;
+    }
+}
+
+__device__ __forceinline__ double dmax8(double v) {
+    v = fmax(v, __shfl_xor(v, 1, 8));
+    v = fmax(v, __shfl_xor(v, 2, 8));
+    return fmax(v, __shfl_xor(v, 4, 8));
+}
+
+template <typename T>
+__device__ __forceinline__ T sum8(T v) {
+    v += __shfl_xor(v, 1, 8);
+    v += __shfl_xor(v, 2, 8);
+    return v + __shfl_xor(v, 4, 8);
+}
+
+__device__ __forceinline__ float exp_nonpos(double x) {   // exp(x), x <= 0
+    return __builtin_amdgcn_exp2f((float)(x * kLog2e));
+}
+
+// One wave per (query, document).  LDS: lu[m], lr[m] = log r, lv[n],
+// lc[n] = log c (doubles), then the rows' corpus word indices col[n].
+__global__ __launch_bounds__(64) void k_sink_lse(SinkArgs g) {
+    extern __shared__ double sm[];
+    const int lane = threadIdx.x;
+    const int64_t item = blockIdx.x;
+    const int nd = g.d_end - g.d_begin;
+    const int qidx = g.qlist[item / nd];
+    const int d = g.d_begin + (int)(item % nd);
+    const QueryDev* qp = g.qd + qidx;
+    const int m = qp->m, ldk = qp->ldk;
+    const double lam = qp->lambda;
+    const auto D = gmem(reinterpret_cast<const double*>(qp->Kt));
+    const int rs = g.sptr[d], n = g.sptr[d + 1] - rs;
+    double* lu = sm;
+    double* lr = lu + m;
+    double* lv = lr + m;
+    double* lc = lv + n;
+    int* col = reinterpret_cast<int*>(lc + n);
+    const auto rq = gmem(qp->r);
+    for (int k = lane; k < m; k += 64) {
+        lr[k] = log((double)rq[k]);
+        lu[k] = log((double)m);           // x = 1/v_r, u = 1/x
+    }
+    for (int i = lane; i < n; i += 64) {
+        lc[i] = log((double)g.scw[rs + i]);
+        col[i] = g.scol[rs + i];
+    }
+    __syncthreads();
+
+    // rows, 8 lanes each: lv_i = log c_i - LSE_k(lu_k - lambda d_ik); on the
+    // final pass also the document's sum_i c_i (sum_k w_ik d_ik) / (sum_k w_ik)
+    const int ri = lane >> 3, j = lane & 7;
+    auto rows = [&](bool final) -> double {
+        double wsum = 0.0;
+        for (int i0 = 0; i0 < n; i0 += 8) {
+            const int i = i0 + ri;
+            const bool ok = i < n;
+            const auto row = D + (int64_t)col[ok ? i : 0] * ldk;
+            double mx = -INFINITY;
+            for (int k = j; k < m; k += 8) mx = fmax(mx, lu[k] - lam * row[k]);
+            mx = dmax8(mx);
+            float s = 0.f;
+            double sd = 0.0;
+            for (int k = j; k < m; k += 8) {
+                const double dk = row[k];
+                const float w = exp_nonpos(lu[k] - lam * dk - mx);
+                s += w;
+                if (final) sd = fma((double)w, dk, sd);
+            }
+            s = sum8(s);
+            if (final) {
+                sd = sum8(sd);
+                if (ok && j == 0) wsum += (double)g.scw[rs + i] * sd / (double)s;
+            } else if (ok && j == 0) {
+                lv[i] = lc[i] - (mx + log((double)s));
+            }
+        }
+        return wsum;
+    };
+    // columns, one lane each: lu_k = log r_k - LSE_i(lv_i - lambda d_ik);
+    // with resid, sum_k |P1_k - r_k| where P1_k = exp(lu_k + LSE_i(...))
+    auto cols = [&](bool resid) -> double {
+        double rsum = 0.0;
+        for (int k = lane; k < m; k += 64) {
+            double mx = -INFINITY;
+            for (int i = 0; i < n; ++i) mx = fmax(mx, lv[i] - lam * D[(int64_t)col[i] * ldk + k]);
+            float s = 0.f;
+            for (int i = 0; i < n; ++i) s += exp_nonpos(lv[i] - lam * D[(int64_t)col[i] * ldk + k] - mx);
+            const double l = mx + log((double)s);
+            if (resid) rsum += fabs(exp(lu[k] + l) - (double)rq[k]);
+            else lu[k] = lr[k] - l;
+        }
+        return rsum;
+    };
+
+    for (int it = 0; it < qp->iters; ++it) {
+        rows(false);
+        __syncthreads();
+        cols(false);
+        __syncthreads();
+    }
+    if (qp->resid) {      // the final v, for the residual's column sums
+        rows(false);
+        __syncthreads();
+    }
+    double wsum = rows(true);
+    double rsum = qp->resid ? cols(true) : 0.0;
+    for (int o = 32; o >= 1; o >>= 1) {
+        wsum += __shfl_xor(wsum, o);
+        rsum += __shfl_xor(rsum, o);
+    }
+    if (lane == 0) {
+        const int doc = g.sdoc[d];
+        gmem(qp->out)[doc] = wsum;
+        if (qp->resid) gmem(qp->resid)[doc] = rsum;
+        if (qp->it_out) gmem(qp->it_out)[doc] = qp->iters;
+    }
+}
+
+}  // namespace
+
+size_t lse_dist_lds_bytes(int ldv) { return sizeof(float) * (size_t)kCols * (ldv + 4); }
+
+size_t lse_sink_lds_bytes(int max_m, int max_n) {
+    return sizeof(double) * 2 * ((size_t)max_m + max_n) + sizeof(int) * (size_t)max_n;
+}
+
+hipError_t launch_dist_lse(const DevCorpus& c, const QueryDev* qd, const int32_t* kofs, int B, int ncols,
+                           hipStream_t s) {
+    LseDistArgs a;
+    a.act = c.act;
+    a.vecs = c.vecs;
+    a.qd = qd;
+    a.kofs = kofs;
+    a.U = c.U;
+    a.ldv = c.ldv;
+    a.B = B;
+    a.ncols = ncols;
+    const size_t lds = lse_dist_lds_bytes(c.ldv);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_dist_lse, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    const dim3 grid((unsigned)((c.U + kRows - 1) / kRows), (unsigned)((ncols + kCols - 1) / kCols));
+    hipLaunchKernelGGL(k_dist_lse, grid, dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sinkhorn_lse(const SinkArgs& a, int max_m, int max_n, hipStream_t s) {
+    const int64_t nitems = (int64_t)a.nq * (a.d_end - a.d_begin);
+    if (nitems <= 0) return hipSuccess;
+    const size_t lds = lse_sink_lds_bytes(max_m, max_n);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_sink_lse, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_sink_lse, dim3((unsigned)nitems), dim3(64), lds, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace wmd

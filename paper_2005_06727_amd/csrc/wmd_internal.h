@@ -78,6 +78,14 @@ struct SinkArgs {
 };
 
 // ---- launchers (return hipError_t of the launch) ----
+// Log-domain iteration: FP64 distance kernel (Kt of each query holds U x ldk
+// doubles) and the log-sum-exp Sinkhorn, one wave per (query, document).
+constexpr size_t kLseMaxLds = 160 * 1024;
+size_t lse_dist_lds_bytes(int ldv);
+size_t lse_sink_lds_bytes(int max_m, int max_n);
+hipError_t launch_dist_lse(const DevCorpus& c, const QueryDev* qd, const int32_t* kofs, int B, int ncols,
+                           hipStream_t s);
+hipError_t launch_sinkhorn_lse(const SinkArgs& a, int max_m, int max_n, hipStream_t s);
 hipError_t launch_prep_norms(const float* rows, int64_t nrows, int ldv, float* norms, hipStream_t s);
 hipError_t launch_prep_bf16(const float* src, uint16_t* dst, float* norms, int64_t nrows, int ldv,
                             hipStream_t s);

@@ -49,7 +49,7 @@ class wmd_corpus_options(C.Structure):
 class wmd_query_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("recompute_below", C.c_float),
                 ("log_domain", C.c_int32), ("iters_per_launch", C.c_int32), ("tile", C.c_int32),
-                ("tol", C.c_float)]
+                ("tol", C.c_float), ("lse", C.c_int32)]
 
 
 class wmd_corpus_info(C.Structure):
@@ -148,7 +148,7 @@ def _ptr(a: np.ndarray, ctype):
 
 
 def _qopts(precision=WMD_DIST_FP32, recompute_below=-1.0, log_domain=False, iters_per_launch=0,
-           tile=-1, tol=0.0):
+           tile=-1, tol=0.0, lse=False):
     o = wmd_query_options()
     _lib.wmd_query_options_init(C.byref(o))
     o.precision = int(precision)
@@ -157,6 +157,7 @@ def _qopts(precision=WMD_DIST_FP32, recompute_below=-1.0, log_domain=False, iter
     o.iters_per_launch = int(iters_per_launch)
     o.tile = int(tile)
     o.tol = float(tol)
+    o.lse = int(bool(lse))
     return o
 
 

@@ -16,8 +16,8 @@ def test_every_declared_function_is_exported():
 
 def test_option_defaults():
     o = wmd.wmd_query_options_init()
-    assert (o.precision, o.recompute_below, o.log_domain, o.iters_per_launch, o.tile, o.tol) == (
-        0, -1.0, 0, 0, -1, 0.0)
+    assert (o.precision, o.recompute_below, o.log_domain, o.iters_per_launch, o.tile, o.tol, o.lse) == (
+        0, -1.0, 0, 0, -1, 0.0, 0)
     c = wmd.wmd_corpus_options_init()
     assert (c.device, c.bf16) == (-1, 0)
 
