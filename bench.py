@@ -18,7 +18,10 @@ carries the 64-query batch on the same corpus (v_r 5-200) served three ways
 (back-to-back plain calls, one batch call, the continuous-batching server),
 with p50/p99 latency under Poisson arrivals.  ``--serve c5`` instead runs the
 served stream on the 100000-document corpus (BF16 distances) against plain
-FP32 calls and prints its own JSON line.
+FP32 calls and prints its own JSON line.  ``--lse`` runs the log-domain
+iteration (FP64 distances and potentials) on the 20000-document precision
+corpus at lambda = 1000, beyond the range of the scaled kernel, and prints its
+own JSON line.
 """
 from __future__ import annotations
 
@@ -37,6 +40,10 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0            # MI355X HBM3E
 PEAK_FP32_VALU_TFLOPS = 157.3    # MI355X FP32 vector (counts packed dual-issue)
 PEAK_FP32_MFMA_TFLOPS = 157.3    # MI355X dense FP32 matrix
+PEAK_FP64_VALU_TFLOPS = 78.6     # MI355X FP64 vector
+# FP32 exponentials (v_exp_f32, a quarter-rate transcendental): 256 CUs x 4 SIMDs
+# x 16 lanes / 4 x 2.4 GHz
+PEAK_EXP_TPS = 256 * 4 * 16 / 4 * 2.4e9 / 1e12
 
 
 def parse():
@@ -54,6 +61,9 @@ def parse():
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                    help="also run one device copy of this many MiB (reference for HBM counters)")
     p.add_argument("--serve", default=None, choices=["c5"], help="run the served-stream benchmark")
+    p.add_argument("--lse", action="store_true",
+                   help="run the log-domain iteration on the precision corpus at lambda = 1000")
+    p.add_argument("--lse-lambda", type=float, default=1000.0)
     p.add_argument("--queries", type=int, default=2000)
     p.add_argument("--qps", type=float, default=0.0, help="offered rate (0: 80%% of plain capacity)")
     p.add_argument("--max-batch", type=int, default=16)
@@ -265,6 +275,81 @@ def serve_main(args):
     print(json.dumps(line), flush=True)
 
 
+def lse_main(args):
+    import torch
+    from oracle import sinkhorn_wmd_lse
+    from paper_2005_06727_amd import synth, wmd
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    wl = synth.make("c4")
+    sp = wl.spec
+    lam, t = args.lse_lambda, sp.iters
+    qs = [(np.ascontiguousarray(q, np.int32), np.ascontiguousarray(w, np.float32)) for q, w in wl.queries]
+    corpus = wmd.Corpus(wl.vecs, wl.doc_ptr, wl.word_ids, wl.weights, device=0)
+    info = corpus.info
+    N, U, nnz, dim = info["N"], info["U"], info["nnz"], info["dim"]
+    h = corpus.handle
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = [torch.empty(N, dtype=torch.float64, device="cuda") for _ in streams]
+
+    def run(n):
+        for i in range(n):
+            q, w = qs[i % len(qs)]
+            wmd.wmd_query_async(h, q, w, lam, t, outs[i % 2], None, streams[i % 2], lse=True)
+
+    run(max(args.warmup // 100, 40))
+    torch.cuda.synchronize()
+    steps = max(args.steps // 50, 80)
+    t0 = time.perf_counter()
+    run(steps)
+    torch.cuda.synchronize()
+    per_q = (time.perf_counter() - t0) / steps
+    # kernel durations, one stream (events on the launching stream)
+    wmd.wmd_set_timing(h, 1)
+    for i in range(40):
+        q, w = qs[i % len(qs)]
+        wmd.wmd_query_async(h, q, w, lam, t, outs[0], None, streams[0], lse=True)
+    torch.cuda.synchronize()
+    tm = wmd.wmd_timing_get(h)
+    wmd.wmd_set_timing(h, 0)
+    dist_us = 1e3 * tm["dist_ms"] / tm["calls"]
+    sink_us = 1e3 * tm["sinkhorn_ms"] / tm["calls"]
+    m_mean = float(np.mean([len(q) for q, _ in qs]))
+    exps = (2 * t + 1) * nnz * m_mean                 # one per (nonzero, query word) per log-sum-exp
+    fl64 = 3.0 * U * m_mean * dim                    # subtract + FMA per (word, query word, dimension)
+    kernels = {
+        "sinkhorn_lse": {"avg_us": sink_us, "bound": "alu", "achieved": exps / (sink_us * 1e-6) / 1e12,
+                         "peak": PEAK_EXP_TPS, "unit": "Texp/s",
+                         "frac": exps / (sink_us * 1e-6) / 1e12 / PEAK_EXP_TPS, "algorithmic_exps": exps},
+        "dist_lse": {"avg_us": dist_us, "bound": "alu", "achieved": fl64 / (dist_us * 1e-6) / 1e12,
+                     "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": fl64 / (dist_us * 1e-6) / 1e12 / PEAK_FP64_VALU_TFLOPS, "algorithmic_flops": fl64},
+    }
+    line = {"metric": "target-doc*Sinkhorn-iters/sec, log-domain iteration", "value": N * t / per_q,
+            "unit": "doc*iters/s", "n_gpus": 1, "steps": steps, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "ms_per_step": per_q * 1e3,
+            "dtype": "f64 distances and potentials, f32 exponentials", "data": "synthetic",
+            "config": {"workload": f"precision corpus (V={info['V']}, dim={dim}, N={N}, nnz={nnz}, U={U}) at "
+                                   f"lambda={lam:g}, {t} iterations, log-domain iteration; {len(qs)} queries "
+                                   f"(v_r {min(len(q) for q, _ in qs)}-{max(len(q) for q, _ in qs)}) in turn "
+                                   f"on 2 streams"},
+            "roofline": kernels["sinkhorn_lse"], "kernels": kernels}
+    if not args.no_cpu_baseline:
+        docs = np.arange(0, N, max(1, N // 1000))
+        sptr, sids, sw = synth.subcorpus(wl.doc_ptr, wl.word_ids, wl.weights, docs)
+        q, w = qs[0]
+        t1 = time.perf_counter()
+        sinkhorn_wmd_lse(wl.vecs, q, w, sptr, sids, sw, lam, t)
+        dt = time.perf_counter() - t1
+        line["cpu_baseline"] = {"value": docs.size * t / dt, "unit": "doc*iters/s", "cores": 1, "kind": "oracle",
+                                "sample": f"FP64 numpy log-domain oracle, 1 query x {docs.size} of the {N} "
+                                          f"documents (every {N // docs.size}th), {t} iterations, one run "
+                                          f"({dt:.2f} s); single-threaded numpy"}
+    corpus.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -274,6 +359,9 @@ def main():
         sys.exit(2)
     if args.serve:
         serve_main(args)
+        return
+    if args.lse:
+        lse_main(args)
         return
 
     import torch

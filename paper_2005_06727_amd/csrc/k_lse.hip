@@ -106,25 +106,61 @@ __global__ __launch_bounds__(256) void k_dist_lse(LseDistArgs a) {
     }
 }
 
-__device__ __forceinline__ double dmax8(double v) {
-    v = fmax(v, __shfl_xor(v, 1, 8));
-    v = fmax(v, __shfl_xor(v, 2, 8));
-    return fmax(v, __shfl_xor(v, 4, 8));
+// Two-pass log-sum-exp in base 2 of a_j = base(j) - lam2 dist(j), j < L:
+// returns the maximum and the FP32 sum of 2^(a_j - max) (with want_sd also
+// the FP64 sum of those terms times dist(j)).  Four independent chains per
+// pass keep the loop from waiting on each maximum or sum.
+template <typename Base, typename Dist>
+__device__ __forceinline__ double lse2(int L, double lam2, Base base, Dist dist, float& s_out, bool want_sd,
+                                       double& sd_out) {
+    double m0 = -INFINITY, m1 = -INFINITY, m2 = -INFINITY, m3 = -INFINITY;
+    int j = 0;
+    for (; j + 4 <= L; j += 4) {
+        m0 = fmax(m0, fma(-lam2, dist(j), base(j)));
+        m1 = fmax(m1, fma(-lam2, dist(j + 1), base(j + 1)));
+        m2 = fmax(m2, fma(-lam2, dist(j + 2), base(j + 2)));
+        m3 = fmax(m3, fma(-lam2, dist(j + 3), base(j + 3)));
+    }
+    for (; j < L; ++j) m0 = fmax(m0, fma(-lam2, dist(j), base(j)));
+    const double mx = fmax(fmax(m0, m1), fmax(m2, m3));
+    float s[4] = {0.f, 0.f, 0.f, 0.f};
+    double sd[4] = {0.0, 0.0, 0.0, 0.0};
+    j = 0;
+    for (; j + 4 <= L; j += 4) {
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const double dj = dist(j + h);
+            const float w = __builtin_amdgcn_exp2f((float)(fma(-lam2, dj, base(j + h)) - mx));
+            s[h] += w;
+            if (want_sd) sd[h] = fma((double)w, dj, sd[h]);
+        }
+    }
+    for (; j < L; ++j) {
+        const double dj = dist(j);
+        const float w = __builtin_amdgcn_exp2f((float)(fma(-lam2, dj, base(j)) - mx));
+        s[0] += w;
+        if (want_sd) sd[0] = fma((double)w, dj, sd[0]);
+    }
+    s_out = (s[0] + s[1]) + (s[2] + s[3]);
+    sd_out = (sd[0] + sd[1]) + (sd[2] + sd[3]);
+    return mx;
 }
 
-template <typename T>
-__device__ __forceinline__ T sum8(T v) {
-    v += __shfl_xor(v, 1, 8);
-    v += __shfl_xor(v, 2, 8);
-    return v + __shfl_xor(v, 4, 8);
+// LDS of one (query, document) pair: lu[m], lr[m] = log r, lv[n], lc[n] =
+// log c (doubles), then col[n] (ints); with STAGED also the document's
+// distance block, column-major with an odd stride (both phases read it
+// without bank conflicts).
+__host__ __device__ inline int lse_stride(int n) { return n | 1; }
+
+__host__ __device__ inline size_t lse_lds_doubles(int m, int n, bool staged) {
+    return 2 * (size_t)m + 2 * (size_t)n + (n + 1) / 2 + (staged ? (size_t)m * lse_stride(n) : 0);
 }
 
-__device__ __forceinline__ float exp_nonpos(double x) {   // exp(x), x <= 0
-    return __builtin_amdgcn_exp2f((float)(x * kLog2e));
-}
-
-// One wave per (query, document).  LDS: lu[m], lr[m] = log r, lv[n],
-// lc[n] = log c (doubles), then the rows' corpus word indices col[n].
+// One wave per (query, document).  Each lane owns a whole row in the row
+// phase and a whole column in the column phase, so no cross-lane reduction
+// is needed; each log-sum-exp takes two passes (the maximum, then the sum of
+// FP32 exponentials below it).
+template <bool STAGED>
 __global__ __launch_bounds__(64) void k_sink_lse(SinkArgs g) {
     extern __shared__ double sm[];
     const int lane = threadIdx.x;
@@ -137,63 +173,63 @@ __global__ __launch_bounds__(64) void k_sink_lse(SinkArgs g) {
     const double lam = qp->lambda;
     const auto D = gmem(reinterpret_cast<const double*>(qp->Kt));
     const int rs = g.sptr[d], n = g.sptr[d + 1] - rs;
+    const int S = lse_stride(n);
+    // the potentials are kept in base 2: lu = log2 u, lv = log2 v, and
+    // lam2 = lambda log2(e), so every exponential is a plain 2^x
+    const double lam2 = lam * kLog2e;
     double* lu = sm;
     double* lr = lu + m;
     double* lv = lr + m;
     double* lc = lv + n;
     int* col = reinterpret_cast<int*>(lc + n);
+    double* Ds = reinterpret_cast<double*>(col) + (n + 1) / 2;   // STAGED: Ds[k * S + i]
     const auto rq = gmem(qp->r);
     for (int k = lane; k < m; k += 64) {
-        lr[k] = log((double)rq[k]);
-        lu[k] = log((double)m);           // x = 1/v_r, u = 1/x
+        lr[k] = log2((double)rq[k]);
+        lu[k] = log2((double)m);          // x = 1/v_r, u = 1/x
     }
     for (int i = lane; i < n; i += 64) {
-        lc[i] = log((double)g.scw[rs + i]);
+        lc[i] = log2((double)g.scw[rs + i]);
         col[i] = g.scol[rs + i];
     }
     __syncthreads();
+    if constexpr (STAGED) {
+        for (int p = lane; p < n * m; p += 64) {
+            const int i = p / m, k = p % m;
+            Ds[k * S + i] = D[(int64_t)col[i] * ldk + k];
+        }
+        __syncthreads();
+    }
+    auto dist = [&](int i, int k) -> double {
+        if constexpr (STAGED) return Ds[k * S + i];
+        else return D[(int64_t)col[i] * ldk + k];
+    };
 
-    // rows, 8 lanes each: lv_i = log c_i - LSE_k(lu_k - lambda d_ik); on the
-    // final pass also the document's sum_i c_i (sum_k w_ik d_ik) / (sum_k w_ik)
-    const int ri = lane >> 3, j = lane & 7;
+    // row i: lv_i = log2 c_i - LSE2_k(lu_k - lam2 d_ik); on the final pass
+    // c_i (sum_k w_ik d_ik) / (sum_k w_ik) instead, summed over the lane's rows
     auto rows = [&](bool final) -> double {
         double wsum = 0.0;
-        for (int i0 = 0; i0 < n; i0 += 8) {
-            const int i = i0 + ri;
-            const bool ok = i < n;
-            const auto row = D + (int64_t)col[ok ? i : 0] * ldk;
-            double mx = -INFINITY;
-            for (int k = j; k < m; k += 8) mx = fmax(mx, lu[k] - lam * row[k]);
-            mx = dmax8(mx);
-            float s = 0.f;
-            double sd = 0.0;
-            for (int k = j; k < m; k += 8) {
-                const double dk = row[k];
-                const float w = exp_nonpos(lu[k] - lam * dk - mx);
-                s += w;
-                if (final) sd = fma((double)w, dk, sd);
-            }
-            s = sum8(s);
-            if (final) {
-                sd = sum8(sd);
-                if (ok && j == 0) wsum += (double)g.scw[rs + i] * sd / (double)s;
-            } else if (ok && j == 0) {
-                lv[i] = lc[i] - (mx + log((double)s));
-            }
+        for (int i = lane; i < n; i += 64) {
+            float s;
+            double sd;
+            const double mx = lse2(m, lam2, [&](int k) { return lu[k]; }, [&](int k) { return dist(i, k); }, s,
+                                   final, sd);
+            if (final) wsum += (double)g.scw[rs + i] * sd / (double)s;
+            else lv[i] = lc[i] - (mx + log2((double)s));
         }
         return wsum;
     };
-    // columns, one lane each: lu_k = log r_k - LSE_i(lv_i - lambda d_ik);
-    // with resid, sum_k |P1_k - r_k| where P1_k = exp(lu_k + LSE_i(...))
+    // column k: lu_k = log2 r_k - LSE2_i(lv_i - lam2 d_ik); with resid,
+    // sum_k |P1_k - r_k| where P1_k = 2^(lu_k + LSE2_i(...))
     auto cols = [&](bool resid) -> double {
         double rsum = 0.0;
         for (int k = lane; k < m; k += 64) {
-            double mx = -INFINITY;
-            for (int i = 0; i < n; ++i) mx = fmax(mx, lv[i] - lam * D[(int64_t)col[i] * ldk + k]);
-            float s = 0.f;
-            for (int i = 0; i < n; ++i) s += exp_nonpos(lv[i] - lam * D[(int64_t)col[i] * ldk + k] - mx);
-            const double l = mx + log((double)s);
-            if (resid) rsum += fabs(exp(lu[k] + l) - (double)rq[k]);
+            float s;
+            double sd;
+            const double mx = lse2(n, lam2, [&](int i) { return lv[i]; }, [&](int i) { return dist(i, k); }, s,
+                                   false, sd);
+            const double l = mx + log2((double)s);
+            if (resid) rsum += fabs(exp2(lu[k] + l) - (double)rq[k]);
             else lu[k] = lr[k] - l;
         }
         return rsum;
@@ -227,8 +263,13 @@ __global__ __launch_bounds__(64) void k_sink_lse(SinkArgs g) {
 
 size_t lse_dist_lds_bytes(int ldv) { return sizeof(float) * (size_t)kCols * (ldv + 4); }
 
+// the documents' distance blocks are staged in LDS when every pair of the
+// launch fits in this much
+constexpr size_t kStageLds = 48 * 1024;
+
 size_t lse_sink_lds_bytes(int max_m, int max_n) {
-    return sizeof(double) * 2 * ((size_t)max_m + max_n) + sizeof(int) * (size_t)max_n;
+    const size_t staged = sizeof(double) * lse_lds_doubles(max_m, max_n, true);
+    return staged <= kStageLds ? staged : sizeof(double) * lse_lds_doubles(max_m, max_n, false);
 }
 
 hipError_t launch_dist_lse(const DevCorpus& c, const QueryDev* qd, const int32_t* kofs, int B, int ncols,
@@ -256,11 +297,14 @@ hipError_t launch_sinkhorn_lse(const SinkArgs& a, int max_m, int max_n, hipStrea
     const int64_t nitems = (int64_t)a.nq * (a.d_end - a.d_begin);
     if (nitems <= 0) return hipSuccess;
     const size_t lds = lse_sink_lds_bytes(max_m, max_n);
+    const bool staged = sizeof(double) * lse_lds_doubles(max_m, max_n, true) <= kStageLds;
+    const void* kern = staged ? (const void*)k_sink_lse<true> : (const void*)k_sink_lse<false>;
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_sink_lse, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_sink_lse, dim3((unsigned)nitems), dim3(64), lds, s, a);
+    if (staged) hipLaunchKernelGGL(k_sink_lse<true>, dim3((unsigned)nitems), dim3(64), lds, s, a);
+    else hipLaunchKernelGGL(k_sink_lse<false>, dim3((unsigned)nitems), dim3(64), lds, s, a);
     return hipGetLastError();
 }
 
