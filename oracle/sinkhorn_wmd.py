@@ -193,7 +193,7 @@ def sinkhorn_wmd_sparse(vecs, qids, qweights, doc_ptr, word_ids, weights,
     document stops its x updates after its own count; column j of x depends
     only on column j, so this is the same as running the documents alone).
 
-    ``tol > 0`` is Algorithm 1's "while x changes" test: after each x update,
+    ``tol > 0`` is Algorithm 1's stopping test (iterate while x still changes): after each x update,
     document j computes rho_j = sum_k r_k |x_new[k, j] / x_old[k, j] - 1| and
     makes no further update once rho_j <= tol (at most ``iters`` updates).
     With ``return_history`` the result gains the number of updates t_j of

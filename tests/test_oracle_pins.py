@@ -271,7 +271,7 @@ def test_input_errors():
         sinkhorn_wmd_sparse(vecs, qids, qw, ptr, ids, w, 1.0, -1)
 
 
-# -- convergence check (Algorithm 1's "while x changes"; rho = row-marginal residual)
+# -- convergence check (Algorithm 1 iterates while x still changes; rho = row-marginal residual)
 
 def _adaptive_case():
     rng = np.random.default_rng(31)
