@@ -78,8 +78,9 @@ class wmd_server_stats(C.Structure):
 
 
 _P = C.c_void_p
-_i32p, _i64p = C.POINTER(C.c_int32), C.POINTER(C.c_int64)
-_f32p, _f64p = C.POINTER(C.c_float), C.POINTER(C.c_double)
+# array arguments travel as plain addresses (the element type is the header's):
+# building a typed ctypes pointer per call costs several microseconds
+_i32p = _i64p = _f32p = _f64p = C.c_void_p
 
 
 def _sig(name, res, *args):
@@ -140,15 +141,17 @@ def _check(rc: int) -> None:
 
 
 def _arr(a, dtype) -> np.ndarray:
+    if type(a) is np.ndarray and a.dtype == dtype and a.flags.c_contiguous:
+        return a
     return np.ascontiguousarray(np.asarray(a), dtype=dtype)
 
 
-def _ptr(a: np.ndarray, ctype):
-    return a.ctypes.data_as(C.POINTER(ctype))
+def _ptr(a: np.ndarray, ctype=None) -> int:
+    """Address of a C-contiguous array (``ctype`` names the element type the C side reads)."""
+    return a.__array_interface__["data"][0]
 
 
-def _qopts(precision=WMD_DIST_FP32, recompute_below=-1.0, log_domain=False, iters_per_launch=0,
-           tile=-1, tol=0.0, lse=False):
+def _make_qopts(precision, recompute_below, log_domain, iters_per_launch, tile, tol, lse):
     o = wmd_query_options()
     _lib.wmd_query_options_init(C.byref(o))
     o.precision = int(precision)
@@ -159,6 +162,22 @@ def _qopts(precision=WMD_DIST_FP32, recompute_below=-1.0, log_domain=False, iter
     o.tol = float(tol)
     o.lse = int(bool(lse))
     return o
+
+
+_DEFAULT_QOPTS = (WMD_DIST_FP32, -1.0, False, 0, -1, 0.0, False)
+_default_qopts = None
+
+
+def _qopts(precision=WMD_DIST_FP32, recompute_below=-1.0, log_domain=False, iters_per_launch=0,
+           tile=-1, tol=0.0, lse=False):
+    global _default_qopts
+    args = (precision, recompute_below, log_domain, iters_per_launch, tile, tol, lse)
+    if args == _DEFAULT_QOPTS:
+        # the library copies the options at the call, so one default object serves every call
+        if _default_qopts is None:
+            _default_qopts = _make_qopts(*args)
+        return _default_qopts
+    return _make_qopts(*args)
 
 
 def _devptr(x) -> Optional[int]:
