@@ -946,8 +946,8 @@ const Shape kShapes[] = {
 };
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 // default shape per query-length class (first entry whose max_m covers m)
-const int kDefaultShapes[] = {8, 2, 4, 5, 6, 7};   // chosen by measurement on the c2-shaped corpus
-const int kAdaptiveShapes[] = {0, 2, 4, 5, 6, 7};  // register tiles only (convergence check)
+const int kDefaultShapes[] = {8, 2, 3, 5, 6, 7};   // chosen by measurement on the c2-shaped corpus
+const int kAdaptiveShapes[] = {0, 2, 3, 5, 6, 7};  // register tiles only (convergence check)
 
 }  // namespace
 
