@@ -106,44 +106,64 @@ __global__ __launch_bounds__(256) void k_dist_lse(LseDistArgs a) {
     }
 }
 
-// Two-pass log-sum-exp in base 2 of a_j = base(j) - lam2 dist(j), j < L:
-// returns the maximum and the FP32 sum of 2^(a_j - max) (with want_sd also
-// the FP64 sum of those terms times dist(j)).  Four independent chains per
-// pass keep the loop from waiting on each maximum or sum.
+// Two-pass log-sum-exp in base 2 of a_j = base(j) - lam2 dist(j), j < len,
+// shared by a group of G consecutive lanes (G a power of two): lane j0 of the
+// group takes j = j0, j0 + G, ...  Returns the maximum and the FP32 sum of
+// 2^(a_j - max) (with want_sd also the FP64 sum of those terms times
+// dist(j)), combined over the group with xor shuffles so every lane of the
+// group holds the same values.  Four independent chains per pass keep the
+// loop from waiting on each maximum or sum.  Every lane of the wave must call
+// it (the shuffles).
 template <typename Base, typename Dist>
-__device__ __forceinline__ double lse2(int L, double lam2, Base base, Dist dist, float& s_out, bool want_sd,
-                                       double& sd_out) {
+__device__ __forceinline__ double lse2(int len, int j0, int G, double lam2, Base base, Dist dist, float& s_out,
+                                       bool want_sd, double& sd_out) {
     double m0 = -INFINITY, m1 = -INFINITY, m2 = -INFINITY, m3 = -INFINITY;
-    int j = 0;
-    for (; j + 4 <= L; j += 4) {
+    int j = j0;
+    for (; j + 3 * G < len; j += 4 * G) {
         m0 = fmax(m0, fma(-lam2, dist(j), base(j)));
-        m1 = fmax(m1, fma(-lam2, dist(j + 1), base(j + 1)));
-        m2 = fmax(m2, fma(-lam2, dist(j + 2), base(j + 2)));
-        m3 = fmax(m3, fma(-lam2, dist(j + 3), base(j + 3)));
+        m1 = fmax(m1, fma(-lam2, dist(j + G), base(j + G)));
+        m2 = fmax(m2, fma(-lam2, dist(j + 2 * G), base(j + 2 * G)));
+        m3 = fmax(m3, fma(-lam2, dist(j + 3 * G), base(j + 3 * G)));
     }
-    for (; j < L; ++j) m0 = fmax(m0, fma(-lam2, dist(j), base(j)));
-    const double mx = fmax(fmax(m0, m1), fmax(m2, m3));
+    for (; j < len; j += G) m0 = fmax(m0, fma(-lam2, dist(j), base(j)));
+    double mx = fmax(fmax(m0, m1), fmax(m2, m3));
+    for (int o = 1; o < G; o <<= 1) mx = fmax(mx, __shfl_xor(mx, o));
     float s[4] = {0.f, 0.f, 0.f, 0.f};
     double sd[4] = {0.0, 0.0, 0.0, 0.0};
-    j = 0;
-    for (; j + 4 <= L; j += 4) {
+    j = j0;
+    for (; j + 3 * G < len; j += 4 * G) {
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
-            const double dj = dist(j + h);
-            const float w = __builtin_amdgcn_exp2f((float)(fma(-lam2, dj, base(j + h)) - mx));
+            const double dj = dist(j + h * G);
+            const float w = __builtin_amdgcn_exp2f((float)(fma(-lam2, dj, base(j + h * G)) - mx));
             s[h] += w;
             if (want_sd) sd[h] = fma((double)w, dj, sd[h]);
         }
     }
-    for (; j < L; ++j) {
+    for (; j < len; j += G) {
         const double dj = dist(j);
         const float w = __builtin_amdgcn_exp2f((float)(fma(-lam2, dj, base(j)) - mx));
         s[0] += w;
         if (want_sd) sd[0] = fma((double)w, dj, sd[0]);
     }
-    s_out = (s[0] + s[1]) + (s[2] + s[3]);
-    sd_out = (sd[0] + sd[1]) + (sd[2] + sd[3]);
+    float st = (s[0] + s[1]) + (s[2] + s[3]);
+    double sdt = (sd[0] + sd[1]) + (sd[2] + sd[3]);
+    for (int o = 1; o < G; o <<= 1) {
+        st += __shfl_xor(st, o);
+        if (want_sd) sdt += __shfl_xor(sdt, o);
+    }
+    s_out = st;
+    sd_out = sdt;
     return mx;
+}
+
+// lanes per log-sum-exp for `items` of them in a wave: 64 over the items
+// rounded up to a power of two, at most 8
+__device__ __forceinline__ int lse_group(int items) {
+    int p = 1;
+    while (p < items) p <<= 1;
+    const int g = 64 / p;
+    return g < 1 ? 1 : (g > 8 ? 8 : g);
 }
 
 // LDS of one (query, document) pair: lu[m], lr[m] = log r, lv[n], lc[n] =
@@ -206,16 +226,24 @@ __global__ __launch_bounds__(64) void k_sink_lse(SinkArgs g) {
     };
 
     // row i: lv_i = log2 c_i - LSE2_k(lu_k - lam2 d_ik); on the final pass
-    // c_i (sum_k w_ik d_ik) / (sum_k w_ik) instead, summed over the lane's rows
+    // c_i (sum_k w_ik d_ik) / (sum_k w_ik) instead, summed over the lane's rows.
+    // Gr lanes per row (Gc per column below), so short documents and queries
+    // still keep most of the wave busy.
+    const int Gr = lse_group(n), Gc = lse_group(m);
     auto rows = [&](bool final) -> double {
         double wsum = 0.0;
-        for (int i = lane; i < n; i += 64) {
+        for (int i0 = 0; i0 < n; i0 += 64 / Gr) {
+            const int i = i0 + lane / Gr;
+            const bool ok = i < n;
+            const int ic = ok ? i : 0;
             float s;
             double sd;
-            const double mx = lse2(m, lam2, [&](int k) { return lu[k]; }, [&](int k) { return dist(i, k); }, s,
-                                   final, sd);
-            if (final) wsum += (double)g.scw[rs + i] * sd / (double)s;
-            else lv[i] = lc[i] - (mx + log2((double)s));
+            const double mx = lse2(m, lane % Gr, Gr, lam2, [&](int k) { return lu[k]; },
+                                   [&](int k) { return dist(ic, k); }, s, final, sd);
+            if (ok && lane % Gr == 0) {
+                if (final) wsum += (double)g.scw[rs + i] * sd / (double)s;
+                else lv[i] = lc[i] - (mx + log2((double)s));
+            }
         }
         return wsum;
     };
@@ -223,14 +251,19 @@ __global__ __launch_bounds__(64) void k_sink_lse(SinkArgs g) {
     // sum_k |P1_k - r_k| where P1_k = 2^(lu_k + LSE2_i(...))
     auto cols = [&](bool resid) -> double {
         double rsum = 0.0;
-        for (int k = lane; k < m; k += 64) {
+        for (int k0 = 0; k0 < m; k0 += 64 / Gc) {
+            const int k = k0 + lane / Gc;
+            const bool ok = k < m;
+            const int kc = ok ? k : 0;
             float s;
             double sd;
-            const double mx = lse2(n, lam2, [&](int i) { return lv[i]; }, [&](int i) { return dist(i, k); }, s,
-                                   false, sd);
+            const double mx = lse2(n, lane % Gc, Gc, lam2, [&](int i) { return lv[i]; },
+                                   [&](int i) { return dist(i, kc); }, s, false, sd);
             const double l = mx + log2((double)s);
-            if (resid) rsum += fabs(exp2(lu[k] + l) - (double)rq[k]);
-            else lu[k] = lr[k] - l;
+            if (ok && lane % Gc == 0) {
+                if (resid) rsum += fabs(exp2(lu[k] + l) - (double)rq[k]);
+                else lu[k] = lr[k] - l;
+            }
         }
         return rsum;
     };

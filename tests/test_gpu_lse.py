@@ -132,3 +132,14 @@ def test_precision_corpus_lambda_1000_sampled(wmd):
         assert np.all(np.isfinite(outs[i]))
     print(f"c4 corpus at lambda = 1000 (log domain): max rel err {worst:.2e}")
     assert worst <= FP32_RTOL
+
+
+def test_server_with_lse_equals_single(ragged, wmd):
+    # the served batches carve their workspaces with the log-domain layout (FP64 distances)
+    (vecs, ptr, ids, w), c = ragged
+    qs = [_query(vecs.shape[0], m, 70 + m) for m in (5, 33, 12, 48)]
+    with wmd.Server(c, lse=True, max_batch=4, max_inflight=2, hbm_budget_bytes=1 << 30) as s:
+        tickets = [s.submit(q, qw, 900.0, 12) for q, qw in qs]
+        got = [s.wait(t)[0] for t in tickets]
+    for (q, qw), d in zip(qs, got):
+        np.testing.assert_array_equal(d, c.query(q, qw, 900.0, 12, lse=True)[0])
