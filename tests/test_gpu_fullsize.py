@@ -99,3 +99,18 @@ def test_served_stream_corpus_sampled(wmd):
           f"plain FP32 (v_r {lens[picks[1]]}) {e32:.2e}")
     assert worst_bf16 <= BF16_RTOL
     assert e32 <= FP32_RTOL
+
+
+def test_paper_corpus_uniform_query_words_sampled(wmd):
+    # the paper-shaped corpus with a query whose words are uniform over the
+    # vocabulary (mostly words no document shares), beside the Zipf queries
+    wl = synth.make("c2")
+    sp = wl.spec
+    q, qw = synth.query(sp.V, 30, np.random.default_rng(2024), "uniform")
+    with wmd.Corpus(wl.vecs, wl.doc_ptr, wl.word_ids, wl.weights, device=0) as c:
+        got, _ = c.query(q, qw, sp.lam, sp.iters)
+    docs = sample_docs(sp.N, 200, 77)
+    want, _ = oracle_docs(wl.vecs, wl.doc_ptr, wl.word_ids, wl.weights, docs, q, qw, sp.lam, sp.iters)
+    e = rel_err(got[docs], want)
+    print(f"c2 corpus, uniform query words (v_r=30): max rel err {e.max():.2e}")
+    assert e.max() <= FP32_RTOL
