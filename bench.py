@@ -216,6 +216,35 @@ def batch_section(wmd, corpus, sp, reps: int = 3) -> dict:
     return out
 
 
+def extensions_section(wmd, corpus, sp, q, qw, calls: int = 200) -> dict:
+    """The convergence-checked iteration and the k-nearest selection on the same
+    query, against the plain query, all synchronous (host in, host out)."""
+    N = corpus.info["N"]
+
+    def per_call(f):
+        for _ in range(20):
+            f()
+        t = time.perf_counter()
+        for _ in range(calls):
+            r = f()
+        return (time.perf_counter() - t) / calls, r
+
+    t_plain, _ = per_call(lambda: corpus.query(q, qw, sp.lam, sp.iters))
+    tol = 1e-3
+    t_ad, (_, _, its) = per_call(lambda: corpus.query_adaptive(q, qw, sp.lam, sp.iters, tol))
+    k = 100
+    t_topk, _ = per_call(lambda: corpus.topk(q, qw, sp.lam, sp.iters, k))
+    return {
+        "what": "synchronous calls on the headline query: per-call wall time",
+        "plain": {"us_per_query": t_plain * 1e6, "doc_iters_per_s": N * sp.iters / t_plain},
+        "convergence_check": {"tol": tol, "max_iters": sp.iters, "mean_iters": float(np.mean(its)),
+                              "docs_stopped_early": float(np.mean(its < sp.iters)),
+                              "us_per_query": t_ad * 1e6,
+                              "doc_iters_per_s": float(np.sum(its)) / t_ad},
+        "topk": {"k": k, "us_per_query": t_topk * 1e6, "difference_us_vs_plain": (t_topk - t_plain) * 1e6},
+    }
+
+
 def serve_main(args):
     """Served stream on the large corpus (BF16 distances, server) vs plain FP32
     synchronous calls, same queries and Poisson arrival times."""
@@ -505,6 +534,7 @@ def main():
     }
     if not args.no_batch:
         line["batch64"] = batch_section(wmd, corpus, sp)
+        line["extensions"] = extensions_section(wmd, corpus, sp, q, qw)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, q, qw, args.cpu_seconds)
     corpus.close()

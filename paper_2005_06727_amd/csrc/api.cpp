@@ -954,7 +954,10 @@ int wmd_query_topk(wmd_corpus* c, const int32_t* qids, const float* qweights, in
     double* rd = nullptr;
     if ((rc = enqueue_topk(c, w, k, c->stream, &ri, &rd))) return rc;
     hipError_t e;
-    const size_t hb = sizeof(double) * k + sizeof(int32_t) * k;
+    // the indices and distances sit in one region of the scratch (indices first,
+    // distances 256-byte aligned after them): one copy brings both
+    const size_t doff = align_up(sizeof(int32_t) * k, 256);
+    const size_t hb = doff + sizeof(double) * k;
     if (hb > w.tkhcap) {
         if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(e, "top-k: wait");
         hfree(w.tk_host);
@@ -963,14 +966,13 @@ int wmd_query_topk(wmd_corpus* c, const int32_t* qids, const float* qweights, in
             return hip_fail(e, "top-k: pinned results");
         w.tkhcap = hb;
     }
-    if ((e = hipMemcpyAsync(w.tk_host, rd, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
-        (e = hipMemcpyAsync(w.tk_host + sizeof(double) * k, ri, sizeof(int32_t) * k, hipMemcpyDeviceToHost,
-                            c->stream)) != hipSuccess)
+    (void)rd;
+    if ((e = hipMemcpyAsync(w.tk_host, ri, hb, hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
         return hip_fail(e, "top-k: download");
     if ((e = hipEventRecord(w.done, c->stream)) != hipSuccess) return hip_fail(e, "top-k: record");
     if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(e, "top-k: execution");
-    std::memcpy(out_dist, w.tk_host, sizeof(double) * k);
-    std::memcpy(out_idx, w.tk_host + sizeof(double) * k, sizeof(int32_t) * k);
+    std::memcpy(out_idx, w.tk_host, sizeof(int32_t) * k);
+    std::memcpy(out_dist, w.tk_host + doff, sizeof(double) * k);
     return WMD_OK;
 }
 
