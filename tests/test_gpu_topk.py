@@ -108,3 +108,27 @@ def test_topk_errors(ragged, wmd):
         with pytest.raises(wmd.WmdError) as e:
             c.topk(q, qw, 10.0, 5, k)
         assert e.value.code == wmd.WMD_EINVAL
+
+
+def test_ties_across_tiles_and_passes(wmd):
+    # 20 000 documents repeating 3 contents: one distance value covers ~6 700
+    # documents, so the first k are all tied and must be the k smallest indices
+    # of that value, across several tiles and a second selection pass
+    rng = np.random.default_rng(12)
+    vecs = synth.embeddings(400, 32, rng)
+    base = [np.array([3, 17, 40], np.int32), np.array([5, 6], np.int32), np.array([100, 7, 8, 9], np.int32)]
+    N = 20000
+    docs = [base[(i * 7) % 3] for i in range(N)]
+    ptr = np.zeros(N + 1, np.int64)
+    ptr[1:] = np.cumsum([len(d) for d in docs])
+    ids = np.concatenate(docs)
+    wts = np.ones(ids.size, np.float32)
+    with wmd.Corpus(vecs, ptr, ids, wts, device=0) as c:
+        q, qw = np.array([3, 5, 200], np.int32), np.array([1, 2, 1], np.float32)
+        full, _ = c.query(q, qw, 10.0, 15)
+        assert len(np.unique(full)) == 3
+        for k in (1000, 2048, 7):
+            idx, dist = c.topk(q, qw, 10.0, 15, k)
+            want_idx, want_dist = knn(full, k)
+            np.testing.assert_array_equal(idx, want_idx)
+            np.testing.assert_array_equal(dist, want_dist)
