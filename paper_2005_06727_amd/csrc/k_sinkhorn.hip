@@ -113,28 +113,6 @@ __device__ __forceinline__ float sum_over_a(float v) {
     return v;
 }
 
-// Sum over the 4 lane rows (lanes l, l^16, l^32, l^48) of four values at once:
-// a reduce-scatter with the gfx950 row swaps leaves row j of t with one of the
-// four sums (each computed once), then the swaps copy every sum to every row,
-// so all copies carry identical bits.  12 VALU ops for 4 values, against 24
-// for four separate xor16 + xor32 butterflies.
-__device__ __forceinline__ void sum_rows4(float& y0, float& y1, float& y2, float& y3) {
-    auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(y0), __float_as_uint(y1), false, false);
-    const float s01 = __uint_as_float(a[0]) + __uint_as_float(a[1]);   // rows 0-1: y0, rows 2-3: y1
-    auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(y2), __float_as_uint(y3), false, false);
-    const float s23 = __uint_as_float(b[0]) + __uint_as_float(b[1]);   // rows 0-1: y2, rows 2-3: y3
-    auto c = __builtin_amdgcn_permlane16_swap(__float_as_uint(s01), __float_as_uint(s23), false, false);
-    const float t = __uint_as_float(c[0]) + __uint_as_float(c[1]);     // rows 0,1,2,3: y0,y2,y1,y3
-    auto d = __builtin_amdgcn_permlane16_swap(__float_as_uint(t), __float_as_uint(t), false, false);
-    // d[0]: rows (0,0,2,2) of t = (y0,y0,y1,y1); d[1]: rows (1,1,3,3) = (y2,y2,y3,y3)
-    auto e = __builtin_amdgcn_permlane32_swap(d[0], d[0], false, false);
-    auto f = __builtin_amdgcn_permlane32_swap(d[1], d[1], false, false);
-    y0 = __uint_as_float(e[0]);
-    y1 = __uint_as_float(e[1]);
-    y2 = __uint_as_float(f[0]);
-    y3 = __uint_as_float(f[1]);
-}
-
 // (K .* M) of a kernel value kk = exp(-lambda (M - n)): kk (n - ln(kk) / lambda),
 // with log2(kk) = exponent + log2(mantissa) (the hardware log2 flushes
 // denormal inputs; the mantissa is always normal, so denormal kk are exact),
@@ -173,58 +151,92 @@ __device__ __forceinline__ float km_row(const float (&kk)[Q], const float (&u)[Q
     return rsum;
 }
 
-// Lane-pair sums of two values at once over lane ^ 16 (ROW = 16) or lane ^ 32
-// (ROW = 32): a swap leaves one value's pair sum in each half, a second swap
-// copies both sums to both halves (each sum computed once, identical bits).
-template <int ROW>
-__device__ __forceinline__ void pair_sum2(float& y0, float& y1) {
-    auto swp = [](uint32_t a, uint32_t b) {
-        if constexpr (ROW == 16) return __builtin_amdgcn_permlane16_swap(a, b, false, false);
-        else return __builtin_amdgcn_permlane32_swap(a, b, false, false);
-    };
-    auto r = swp(__float_as_uint(y0), __float_as_uint(y1));
-    const float t = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-    auto e = swp(__float_as_uint(t), __float_as_uint(t));
-    y0 = __uint_as_float(e[0]);
-    y1 = __uint_as_float(e[1]);
+// Reduce-scatter over lane bit BETA (2..5) of N values: afterwards the lanes
+// with that bit clear hold, in v[0, N/2), the pair sums of the first half,
+// the lanes with it set those of the second half.  Each sum is formed on one
+// lane only, so the copies that the matching all-gather hands out agree bit
+// for bit.
+template <int BETA, int N>
+__device__ __forceinline__ void rs_bit(float* v) {
+    static_assert(BETA >= 2 && BETA <= 5 && N % 2 == 0, "lane bits 2..5, even counts");
+    constexpr int H = N / 2;
+    if constexpr (BETA >= 4) {
+        // the row swap exchanges the second half of one lane pair's registers
+        // with the first half of the other's
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            const uint32_t lo = __float_as_uint(v[j]), hi = __float_as_uint(v[j + H]);
+            auto r = (BETA == 4) ? __builtin_amdgcn_permlane16_swap(lo, hi, false, false)
+                                 : __builtin_amdgcn_permlane32_swap(lo, hi, false, false);
+            v[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+        }
+    } else {
+        const bool up = (__lane_id() >> BETA) & 1;
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            const float keep = up ? v[j + H] : v[j];
+            const float send = up ? v[j] : v[j + H];
+            float other;
+            if constexpr (BETA == 2)   // lane ^ 4 through the LDS crossbar
+                other = __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(send), 0x101F));
+            else                       // row_ror:8 == lane ^ 8 within a row
+                other = dpp<0x128>(send);
+            v[j] = keep + other;
+        }
+    }
 }
 
-// sum_over_a for K values at once, step-major; K even
-template <int R, int C, int K>
-__device__ __forceinline__ void sum_over_a_n(float* y) {
-    constexpr int T = R * C;
-    if constexpr (C <= 1 && T > 1) {
+// All-gather over lane bit BETA: v[0, N) holds the first-half values on the
+// lanes with the bit clear and the second-half values on the others;
+// afterwards every lane holds all 2N values in order.
+template <int BETA, int N>
+__device__ __forceinline__ void ag_bit(float* v) {
+    static_assert(BETA >= 2 && BETA <= 5, "lane bits 2..5");
+    if constexpr (BETA >= 4) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) y[k] += dpp<0xB1>(y[k]);
-    }
-    if constexpr (C <= 2 && T > 2) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) y[k] += dpp<0x4E>(y[k]);
-    }
-    if constexpr (C <= 4 && T > 4) {
-        // lane ^ 4 through the LDS crossbar (no LDS memory, no VALU slot)
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-            y[k] += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(y[k]), 0x101F));
-    }
-    if constexpr (C <= 8 && T > 8) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) y[k] += dpp<0x128>(y[k]);
-    }
-    if constexpr (T == 64 && K % 4 == 0) {
-#pragma unroll
-        for (int k = 0; k < K; k += 4) sum_rows4(y[k], y[k + 1], y[k + 2], y[k + 3]);
-    } else {
-        if constexpr (T > 16) {
-#pragma unroll
-            for (int k = 0; k < K; k += 2) pair_sum2<16>(y[k], y[k + 1]);
+        for (int j = 0; j < N; ++j) {
+            const uint32_t w = __float_as_uint(v[j]);
+            auto r = (BETA == 4) ? __builtin_amdgcn_permlane16_swap(w, w, false, false)
+                                 : __builtin_amdgcn_permlane32_swap(w, w, false, false);
+            v[j] = __uint_as_float(r[0]);
+            v[j + N] = __uint_as_float(r[1]);
         }
-        if constexpr (T > 32) {
+    } else {
+        // lanes with the bit clear sit in banks 0, 2 (BETA 2) or 0, 1 (BETA 3)
+        // of each 16-lane row and read their partner with row_shl; the others
+        // read theirs with row_shr; lanes outside the bank mask keep their own
+        constexpr int SHL = (BETA == 2) ? 0x104 : 0x108, SHR = (BETA == 2) ? 0x114 : 0x118;
+        constexpr int LO = (BETA == 2) ? 0x5 : 0x3, HI = (BETA == 2) ? 0xA : 0xC;
 #pragma unroll
-            for (int k = 0; k < K; k += 2) pair_sum2<32>(y[k], y[k + 1]);
+        for (int j = 0; j < N; ++j) {
+            const int w = __float_as_int(v[j]);
+            v[j + N] = __int_as_float(__builtin_amdgcn_update_dpp(w, w, SHL, 0xF, LO, false));
+            v[j] = __int_as_float(__builtin_amdgcn_update_dpp(w, w, SHR, 0xF, HI, false));
         }
     }
 }
+
+// Reduce-scatter over lane bits LO .. LO+NB-1, highest first: N values become
+// N >> NB, the lane whose bits read i in that field keeping values
+// [i (N >> NB), (i + 1) (N >> NB)) of the sums.
+template <int LO, int NB, int N>
+__device__ __forceinline__ void rs_bits(float* v) {
+    if constexpr (NB > 0) {
+        rs_bit<LO + NB - 1, N>(v);
+        rs_bits<LO, NB - 1, N / 2>(v);
+    }
+}
+
+// The inverse spread: all-gather over lane bits LO .. LO+NB-1, lowest first.
+template <int LO, int NB, int N>
+__device__ __forceinline__ void ag_bits(float* v) {
+    if constexpr (NB > 0) {
+        ag_bit<LO, N>(v);
+        ag_bits<LO + 1, NB - 1, N * 2>(v);
+    }
+}
+
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 
 template <int T>
 __device__ __forceinline__ double team_sum_f64(double v) {
@@ -255,6 +267,15 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
                                           float* s_rho) {
     constexpr int T = R * C;
     constexpr int Q4 = Q / 4;
+    // The SpMM's column sums are reduce-scattered over the R lanes of a column
+    // group (lane bits LC .. LC+LR-1), so lane (a, b) owns F of its Q columns,
+    // kb + a F + f: it alone forms their sums, x and u = 1/x, and the u values
+    // are then spread back to the group.  One reciprocal per column instead of
+    // R copies.
+    constexpr int LC = ilog2(C), LR = ilog2(R);
+    constexpr int F = Q / R;
+    static_assert((1 << LC) == C && (1 << LR) == R && C >= 4 && Q % R == 0, "team shape");
+    const int kf = kb + a * F;   // first owned column
 
     // A and every per-row / per-column vector are zero outside the document's
     // n x m block, except that a padded row holds 1 in column 0 (which every
@@ -340,29 +361,35 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
     // convergence check (uniform over the launch: one tol per call)
     const float tol = qp->tol;
     const bool adaptive = tol > 0.f;
-    float x[Q], rinv[Q], rq[Q];
+    float x[F], rinv[F], rq[F];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const int k = kb + q;
+    for (int f = 0; f < F; ++f) {
+        const int k = kf + f;
         const bool kv = k < m;
         const int kc = kv ? k : 0;
         const float ri = rinvp[kc];
         const float rv = rp[kc];
-        rinv[q] = kv ? ri : 0.f;
-        rq[q] = (kv && adaptive) ? rv : 0.f;
-        x[q] = kv ? 1.0f / (float)m : 1.f;
+        rinv[f] = kv ? ri : 0.f;
+        rq[f] = (kv && adaptive) ? rv : 0.f;
+        x[f] = kv ? 1.0f / (float)m : 1.f;
     }
     if (g.it_begin != 0) {
         const auto xp = gmem(qp->x) + (int64_t)d * ldk;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const bool kv = kb + q < m;
-            const float xv = xp[kv ? kb + q : 0];
-            x[q] = kv ? xv : 1.f;
+        for (int f = 0; f < F; ++f) {
+            const bool kv = kf + f < m;
+            const float xv = xp[kv ? kf + f : 0];
+            x[f] = kv ? xv : 1.f;
         }
     }
 
-    float u[Q], s[PN], v[PN], y[Q];
+    // u = 1/x on the owned columns (uo), spread to all Q columns of the lane (u)
+    float u[Q], uo[F], s[PN], v[PN], y[Q];
+    auto make_u = [&](void) {
+#pragma unroll
+        for (int f = 0; f < F; ++f) uo[f] = u[f] = rcp(x[f]);
+        ag_bits<LC, LR, F>(u);
+    };
     int par = 0;
     bool done = false;
     int t_done = g.it_begin;
@@ -403,7 +430,8 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
         for (int p = 0; p < PN; ++p) v[p] = cval[p] * s[p];
     };
 
-    // y = A^T v summed over the team's rows (lanes a)
+    // y = A^T v summed over the team's rows (lanes a), the owned columns'
+    // sums left in y[0, F)
     auto spmm = [&](void) {
 #pragma unroll
         for (int q = 0; q < Q; ++q) y[q] = A[0][q] * v[0];
@@ -413,7 +441,7 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
             for (int q = 0; q < Q; ++q) y[q] = fmaf(A[p][q], v[p], y[q]);
         }
         __builtin_amdgcn_sched_barrier(0);
-        sum_over_a_n<R, C, Q>(y);
+        rs_bits<LC, LR, Q>(y);
         __builtin_amdgcn_sched_barrier(0);
     };
 
@@ -422,8 +450,7 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
             // a wave leaves once every team in it has converged
             if (adaptive && __builtin_amdgcn_ballot_w64(!done) == 0) break;
         }
-#pragma unroll
-        for (int q = 0; q < Q; ++q) u[q] = rcp(x[q]);
+        make_u();
         sddmm();
         spmm();
         if (!adaptive) {
@@ -431,19 +458,21 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
             // (same barriers); a team past its own count computes but keeps x
             if (W == 1 || it < my_end) {
 #pragma unroll
-                for (int q = 0; q < Q; ++q) x[q] = fmaf(y[q], rinv[q], kXPad);
+                for (int f = 0; f < F; ++f) x[f] = fmaf(y[f], rinv[f], kXPad);
                 t_done = it + 1;
             }
         } else {
-            // rho = sum_k r_k |x_new / x_old - 1|, with u = 1 / x_old from above
-            float xn[Q];
+            // rho = sum_k r_k |x_new / x_old - 1|, with u = 1 / x_old from above,
+            // over the owned columns, then over the whole team
+            float xn[F];
             float rho = 0.f;
 #pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                xn[q] = fmaf(y[q], rinv[q], kXPad);
-                rho = fmaf(rq[q], fabsf(xn[q] * u[q] - 1.f), rho);
+            for (int f = 0; f < F; ++f) {
+                xn[f] = fmaf(y[f], rinv[f], kXPad);
+                rho = fmaf(rq[f], fabsf(xn[f] * uo[f] - 1.f), rho);
             }
             sum_over_b_n<C, 1>(&rho);
+            rho = sum_over_a<R, C>(rho);
             if constexpr (W > 1) {
                 if (b == 0 && a == 0) s_rho[team * W + wi] = rho;
                 __syncthreads();
@@ -452,7 +481,7 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
             }
             if (!done && (W == 1 || it < my_end)) {
 #pragma unroll
-                for (int q = 0; q < Q; ++q) x[q] = xn[q];
+                for (int f = 0; f < F; ++f) x[f] = xn[f];
                 t_done = it + 1;
                 done = rho <= tol;
             }
@@ -461,27 +490,26 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
     if (g.final_step && qp->it_out && valid && tl == 0 && wi == 0) gmem(qp->it_out)[doc] = t_done;
 
     if (!g.final_step) {
-        if (valid && a == 0) {
+        if (valid) {
 #pragma unroll
-            for (int q = 0; q < Q; ++q)
-                if (kb + q < m) gmem(qp->x)[(int64_t)d * ldk + kb + q] = x[q];
+            for (int f = 0; f < F; ++f)
+                if (kf + f < m) gmem(qp->x)[(int64_t)d * ldk + kf + f] = x[f];
         }
         return;
     }
 
     // final step: u = 1/x (finite on padded columns, where A is zero), v = c / (K^T u)
-#pragma unroll
-    for (int q = 0; q < Q; ++q) u[q] = rcp(x[q]);
+    make_u();
     sddmm();
 
     double rho = 0.0;
     const bool want_resid = valid && qp->resid != nullptr;
     if (__builtin_amdgcn_readfirstlane((int)(qp->resid != nullptr))) {
         spmm();
-        if (want_resid && a == 0) {
+        if (want_resid) {
 #pragma unroll
-            for (int q = 0; q < Q; ++q)
-                if (kb + q < m) rho += fabs((double)u[q] * (double)y[q] - (double)gmem(qp->r)[kb + q]);
+            for (int f = 0; f < F; ++f)
+                if (kf + f < m) rho += fabs((double)uo[f] * (double)y[f] - (double)gmem(qp->r)[kf + f]);
         }
     }
 
