@@ -106,34 +106,48 @@ __global__ __launch_bounds__(256) void k_dist_lse(LseDistArgs a) {
     }
 }
 
+// independent chains per pass of a log-sum-exp
+constexpr int kLseChains = 8;
+
 // Two-pass log-sum-exp in base 2 of a_j = base(j) - lam2 dist(j), j < len,
 // shared by a group of G consecutive lanes (G a power of two): lane j0 of the
 // group takes j = j0, j0 + G, ...  Returns the maximum and the FP32 sum of
 // 2^(a_j - max) (with want_sd also the FP64 sum of those terms times
 // dist(j)), combined over the group with xor shuffles so every lane of the
-// group holds the same values.  Four independent chains per pass keep the
-// loop from waiting on each maximum or sum.  Every lane of the wave must call
+// group holds the same values.  kLseChains independent chains per pass keep
+// the loop from waiting on each maximum or sum.  Every lane of the wave must call
 // it (the shuffles).
 template <typename Base, typename Dist>
 __device__ __forceinline__ double lse2(int len, int j0, int G, double lam2, Base base, Dist dist, float& s_out,
                                        bool want_sd, double& sd_out) {
-    double m0 = -INFINITY, m1 = -INFINITY, m2 = -INFINITY, m3 = -INFINITY;
-    int j = j0;
-    for (; j + 3 * G < len; j += 4 * G) {
-        m0 = fmax(m0, fma(-lam2, dist(j), base(j)));
-        m1 = fmax(m1, fma(-lam2, dist(j + G), base(j + G)));
-        m2 = fmax(m2, fma(-lam2, dist(j + 2 * G), base(j + 2 * G)));
-        m3 = fmax(m3, fma(-lam2, dist(j + 3 * G), base(j + 3 * G)));
-    }
-    for (; j < len; j += G) m0 = fmax(m0, fma(-lam2, dist(j), base(j)));
-    double mx = fmax(fmax(m0, m1), fmax(m2, m3));
-    for (int o = 1; o < G; o <<= 1) mx = fmax(mx, __shfl_xor(mx, o));
-    float s[4] = {0.f, 0.f, 0.f, 0.f};
-    double sd[4] = {0.0, 0.0, 0.0, 0.0};
-    j = j0;
-    for (; j + 3 * G < len; j += 4 * G) {
+    constexpr int NCH = kLseChains;
+    double mc[NCH];
 #pragma unroll
-        for (int h = 0; h < 4; ++h) {
+    for (int h = 0; h < NCH; ++h) mc[h] = -INFINITY;
+    int j = j0;
+    for (; j + (NCH - 1) * G < len; j += NCH * G) {
+#pragma unroll
+        for (int h = 0; h < NCH; ++h) mc[h] = fmax(mc[h], fma(-lam2, dist(j + h * G), base(j + h * G)));
+    }
+    for (; j < len; j += G) mc[0] = fmax(mc[0], fma(-lam2, dist(j), base(j)));
+#pragma unroll
+    for (int w = NCH / 2; w >= 1; w /= 2) {
+#pragma unroll
+        for (int h = 0; h < w; ++h) mc[h] = fmax(mc[h], mc[h + w]);
+    }
+    double mx = mc[0];
+    for (int o = 1; o < G; o <<= 1) mx = fmax(mx, __shfl_xor(mx, o));
+    float s[NCH];
+    double sd[NCH];
+#pragma unroll
+    for (int h = 0; h < NCH; ++h) {
+        s[h] = 0.f;
+        sd[h] = 0.0;
+    }
+    j = j0;
+    for (; j + (NCH - 1) * G < len; j += NCH * G) {
+#pragma unroll
+        for (int h = 0; h < NCH; ++h) {
             const double dj = dist(j + h * G);
             const float w = __builtin_amdgcn_exp2f((float)(fma(-lam2, dj, base(j + h * G)) - mx));
             s[h] += w;
@@ -146,8 +160,16 @@ __device__ __forceinline__ double lse2(int len, int j0, int G, double lam2, Base
         s[0] += w;
         if (want_sd) sd[0] = fma((double)w, dj, sd[0]);
     }
-    float st = (s[0] + s[1]) + (s[2] + s[3]);
-    double sdt = (sd[0] + sd[1]) + (sd[2] + sd[3]);
+#pragma unroll
+    for (int w = NCH / 2; w >= 1; w /= 2) {
+#pragma unroll
+        for (int h = 0; h < w; ++h) {
+            s[h] += s[h + w];
+            sd[h] += sd[h + w];
+        }
+    }
+    float st = s[0];
+    double sdt = sd[0];
     for (int o = 1; o < G; o <<= 1) {
         st += __shfl_xor(st, o);
         if (want_sd) sdt += __shfl_xor(sdt, o);

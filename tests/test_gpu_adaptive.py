@@ -66,6 +66,24 @@ def test_adaptive_counts_and_distances(ragged, wmd, m, tile):
     np.testing.assert_allclose(res, wres, rtol=1e-2, atol=1e-6)
 
 
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, 6, 7])   # the register tiles
+def test_adaptive_every_tile_shape(ragged, wmd, tile):
+    # the stop decision sums rho over every lane of a team (each lane owns some
+    # columns), across waves for the multi-wave shapes
+    from tests.test_gpu_parity import TILE_MAX_M
+    (vecs, ptr, ids, w), c = ragged
+    m = TILE_MAX_M[tile]
+    rng = np.random.default_rng(300 + tile)
+    q = rng.choice(vecs.shape[0], m, replace=False).astype(np.int32)
+    qw = rng.random(m, dtype=np.float32) + 0.1
+    lam, max_iters, tol = 8.0, 40, 2e-3
+    d, _, t = c.query_adaptive(q, qw, lam, max_iters, tol, tile=tile)
+    _, _, _, hist = sinkhorn_wmd_sparse(vecs, q, qw, ptr, ids, w, lam, max_iters, return_history=True)
+    check_counts(t, hist, tol, max_iters)
+    want, _ = sinkhorn_wmd_sparse(vecs, q, qw, ptr, ids, w, lam, t.astype(np.int64))
+    assert rel_err(d, want).max() <= FP32_RTOL
+
+
 def test_tol_zero_is_the_fixed_iteration(ragged, wmd):
     (vecs, ptr, ids, w), c = ragged
     q, qw = np.arange(3, 40, 3, dtype=np.int32), np.ones(13, np.float32)
