@@ -71,7 +71,8 @@ typedef struct wmd_query_options {
                                  launch; k > 0: at most k iterations per launch, x kept
                                  in device memory between launches */
     int32_t tile;             /* Sinkhorn launch shape: -1 picks by query length; 0..7
-                                 forces that register tile (WMD_EINVAL when the query is
+                                 and 11 force that register tile, 8..10 that row-lane
+                                 tile (WMD_EINVAL when the query is
                                  longer than the tile holds); -2 uses the streaming
                                  kernel for every document.  Results are identical
                                  between calls with the same tile, and agree across

@@ -13,10 +13,13 @@
 // Per team of R x C lanes (lane (a, b)), lane (a, b) holds
 //   A[a + R p][kb + q] for p < P, q < Q, with kb = (wave-in-team * C + b) * Q,
 // i.e. rows strided over a and a contiguous block of Q columns per b.
-//   u     = 1 / x                        (columns; every a holds a copy)
+//   u     = 1 / x                        (formed on the column's owner lane,
+//                                         then copied to every a)
 //   s_i   = sum_k A[i][k] u_k            (partial over q, then summed over b)
 //   v_i   = c_i / s_i                    (rows; every b holds a copy)
-//   x_k   = (1 / r_k) sum_i A[i][k] v_i  (partial over p, then summed over a)
+//   x_k   = (1 / r_k) sum_i A[i][k] v_i  (partial over p, then reduce-scattered
+//                                         over a: each column's sum, x and u
+//                                         are formed on one owner lane)
 // Final: u = 1/x, v = c / (A u), WMD = sum_{i,k} ((K .* M)[i][k] u_k) v_i with
 // the products and each lane's sum over its (at most 8) columns of a row in
 // FP32 and the sum beyond in FP64, where K .* M is rebuilt from the
@@ -236,6 +239,25 @@ __device__ __forceinline__ void ag_bits(float* v) {
     }
 }
 
+// All-reduce of N values over lane bits LO .. LO+NB-1 (xor butterflies, so
+// both partners of a step get the same bits).
+template <int LO, int NB, int N>
+__device__ __forceinline__ void allreduce_bits(float* v) {
+    if constexpr (NB > 0) {
+        static_assert(LO >= 0 && LO <= 5, "lane bits 0..5");
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            if constexpr (LO == 0) v[i] += dpp<0xB1>(v[i]);
+            else if constexpr (LO == 1) v[i] += dpp<0x4E>(v[i]);
+            else if constexpr (LO == 2) v[i] += xor4(v[i]);
+            else if constexpr (LO == 3) v[i] += dpp<0x128>(v[i]);
+            else if constexpr (LO == 4) v[i] = add_xor16(v[i]);
+            else v[i] = add_xor32(v[i]);
+        }
+        allreduce_bits<LO + 1, NB - 1, N>(v);
+    }
+}
+
 constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 
 template <int T>
@@ -269,13 +291,18 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
     constexpr int Q4 = Q / 4;
     // The SpMM's column sums are reduce-scattered over the R lanes of a column
     // group (lane bits LC .. LC+LR-1), so lane (a, b) owns F of its Q columns,
-    // kb + a F + f: it alone forms their sums, x and u = 1/x, and the u values
-    // are then spread back to the group.  One reciprocal per column instead of
-    // R copies.
-    constexpr int LC = ilog2(C), LR = ilog2(R);
-    constexpr int F = Q / R;
-    static_assert((1 << LC) == C && (1 << LR) == R && C >= 4 && Q % R == 0, "team shape");
-    const int kf = kb + a * F;   // first owned column
+    // kb + (a >> ARB) F + f: it forms their sums, x and u = 1/x, and the u
+    // values are then spread back to the group.  With more row lanes than
+    // columns (R > Q) the lowest ARB row-lane bits are all-reduced instead, so
+    // 2^ARB lanes form each owned column identically and one of them (lead)
+    // counts it in the residuals and stores it.
+    constexpr int LC = ilog2(C), LR = ilog2(R), LQ = ilog2(Q);
+    constexpr int RSB = (LR < LQ) ? LR : LQ;
+    constexpr int ARB = LR - RSB;
+    constexpr int F = Q >> RSB;
+    static_assert((1 << LC) == C && (1 << LR) == R && (1 << LQ) == Q && C >= 4, "team shape");
+    const int kf = kb + (a >> ARB) * F;              // first owned column
+    const bool lead = (a & ((1 << ARB) - 1)) == 0;
 
     // A and every per-row / per-column vector are zero outside the document's
     // n x m block, except that a padded row holds 1 in column 0 (which every
@@ -370,7 +397,7 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
         const float ri = rinvp[kc];
         const float rv = rp[kc];
         rinv[f] = kv ? ri : 0.f;
-        rq[f] = (kv && adaptive) ? rv : 0.f;
+        rq[f] = (kv && adaptive && lead) ? rv : 0.f;
         x[f] = kv ? 1.0f / (float)m : 1.f;
     }
     if (g.it_begin != 0) {
@@ -388,7 +415,7 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
     auto make_u = [&](void) {
 #pragma unroll
         for (int f = 0; f < F; ++f) uo[f] = u[f] = rcp(x[f]);
-        ag_bits<LC, LR, F>(u);
+        ag_bits<LC + ARB, RSB, F>(u);
     };
     int par = 0;
     bool done = false;
@@ -441,7 +468,8 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
             for (int q = 0; q < Q; ++q) y[q] = fmaf(A[p][q], v[p], y[q]);
         }
         __builtin_amdgcn_sched_barrier(0);
-        rs_bits<LC, LR, Q>(y);
+        rs_bits<LC + ARB, RSB, Q>(y);
+        allreduce_bits<LC, ARB, F>(y);
         __builtin_amdgcn_sched_barrier(0);
     };
 
@@ -490,7 +518,7 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
     if (g.final_step && qp->it_out && valid && tl == 0 && wi == 0) gmem(qp->it_out)[doc] = t_done;
 
     if (!g.final_step) {
-        if (valid) {
+        if (valid && lead) {
 #pragma unroll
             for (int f = 0; f < F; ++f)
                 if (kf + f < m) gmem(qp->x)[(int64_t)d * ldk + kf + f] = x[f];
@@ -506,7 +534,7 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
     const bool want_resid = valid && qp->resid != nullptr;
     if (__builtin_amdgcn_readfirstlane((int)(qp->resid != nullptr))) {
         spmm();
-        if (want_resid) {
+        if (want_resid && lead) {
 #pragma unroll
             for (int f = 0; f < F; ++f)
                 if (kf + f < m) rho += fabs((double)uo[f] * (double)y[f] - (double)gmem(qp->r)[kf + f]);
@@ -598,10 +626,10 @@ __device__ __forceinline__ void sink_dispatch(const int pr, Args&&... args) {
     }
 }
 
-// Occupancy targets: 3 waves per SIMD for 8 rows per lane, 2 for 16; the
-// multi-wave teams take what their registers allow.
+// Occupancy targets: 5 waves per SIMD for 4 rows per lane, 3 for 8, 2 for
+// 16; the multi-wave teams take what their registers allow.
 template <int R, int C, int P, int Q, int W>
-__global__ __launch_bounds__(256, (W > 1) ? 1 : (P >= 16) ? 2 : 3) void k_sink(SinkArgs g) {
+__global__ __launch_bounds__(256, (W > 1) ? 1 : (P >= 16) ? 2 : (P <= 4) ? 5 : 3) void k_sink(SinkArgs g) {
     constexpr int T = R * C;
     static_assert(W == 1 || T == 64, "multi-wave teams use whole waves");
     static_assert(Q % 4 == 0, "columns are loaded as float4");
@@ -971,6 +999,7 @@ const Shape kShapes[] = {
     make_rows_shape<16, 1>(),        // 8: m <= 16,  row lanes
     make_rows_shape<32, 1>(),        // 9: m <= 32,  row lanes
     make_rows_shape<64, 1>(),        // 10: m <= 64, row lanes
+    make_shape<16, 4, 4, 8, 1>(),    // 11: m <= 32,  one wave per document
 };
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 // default shape per query-length class (first entry whose max_m covers m)
