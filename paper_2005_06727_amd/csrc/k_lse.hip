@@ -23,8 +23,8 @@ namespace wmd {
 
 namespace {
 
-constexpr int kRows = 8;       // corpus rows per distance block
-constexpr int kCols = 32;      // query columns per distance block
+constexpr int kRows = 256;     // corpus rows per distance block (one per thread)
+constexpr int kCols = 8;       // query columns per distance block (all in each thread)
 constexpr double kLog2e = 1.4426950408889634;
 
 struct LseDistArgs {
@@ -49,17 +49,17 @@ __device__ int query_of_col(const int32_t* kofs, int B, int c) {
     return lo;
 }
 
-// d[i, c] = sqrt(sum_d (E[word(i), d] - E[qid(c), d])^2) in FP64 for 8 corpus
-// rows x 32 global query columns per block; thread (row rl, column cl).  The
-// 32 query rows are staged in LDS (FP32, row stride ldv + 4).  Columns
-// m_b <= k < ldk_b are written as zeros.
+// d[i, c] = sqrt(sum_d (E[word(i), d] - E[qid(c), d])^2) in FP64 for 256
+// corpus rows x 8 global query columns per block: thread t takes corpus row
+// t (streamed from memory, its own row per lane) against all 8 columns, whose
+// query rows are staged in LDS (FP32, row stride ldv + 4) and read as
+// broadcasts.  Columns m_b <= k < ldk_b are written as zeros.
 __global__ __launch_bounds__(256) void k_dist_lse(LseDistArgs a) {
     extern __shared__ float4 qsh4[];
     float* qsh = reinterpret_cast<float*>(qsh4);
     __shared__ int64_t qrow[kCols];     // vocabulary row of each column, -1 for padding
     __shared__ int qb[kCols], qk[kCols];
     const int tid = threadIdx.x;
-    const int cl = tid % kCols, rl = tid / kCols;
     const int c0 = blockIdx.y * kCols;
     const int stride = a.ldv + 4;
     if (tid < kCols) {
@@ -84,25 +84,33 @@ __global__ __launch_bounds__(256) void k_dist_lse(LseDistArgs a) {
         *reinterpret_cast<float4*>(qsh + cc * stride + 4 * e) = v;
     }
     __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * kRows + rl;
-    const int c = c0 + cl;
-    const auto arow = gmem(a.act) + (i < a.U ? i : 0) * a.ldv;
-    const float* brow = qsh + cl * stride;
-    double acc = 0.0;
+    const int64_t i = (int64_t)blockIdx.x * kRows + tid;
+    const auto arow = gmem(a.act) + (i < a.U ? i : 0) * a.ldv;   // rows beyond U read row 0, not stored
+    double acc[kCols];
+#pragma unroll
+    for (int j = 0; j < kCols; ++j) acc[j] = 0.0;
     for (int e = 0; e < q4; ++e) {
         const float4 x = ld4(arow + 4 * e);
-        const float4 y = *reinterpret_cast<const float4*>(brow + 4 * e);
-        const double d0 = (double)x.x - (double)y.x, d1 = (double)x.y - (double)y.y;
-        const double d2 = (double)x.z - (double)y.z, d3 = (double)x.w - (double)y.w;
-        acc = fma(d0, d0, acc);
-        acc = fma(d1, d1, acc);
-        acc = fma(d2, d2, acc);
-        acc = fma(d3, d3, acc);
+#pragma unroll
+        for (int j = 0; j < kCols; ++j) {
+            const float4 y = *reinterpret_cast<const float4*>(qsh + j * stride + 4 * e);
+            const double d0 = (double)x.x - (double)y.x, d1 = (double)x.y - (double)y.y;
+            const double d2 = (double)x.z - (double)y.z, d3 = (double)x.w - (double)y.w;
+            acc[j] = fma(d0, d0, acc[j]);
+            acc[j] = fma(d1, d1, acc[j]);
+            acc[j] = fma(d2, d2, acc[j]);
+            acc[j] = fma(d3, d3, acc[j]);
+        }
     }
-    if (i < a.U && c < a.ncols) {
-        const QueryDev& q = a.qd[qb[cl]];
-        double* D = reinterpret_cast<double*>(q.Kt);
-        gmem(D)[i * q.ldk + qk[cl]] = qrow[cl] >= 0 ? sqrt(acc) : 0.0;
+    if (i < a.U) {
+#pragma unroll
+        for (int j = 0; j < kCols; ++j) {
+            if (c0 + j < a.ncols) {
+                const QueryDev& q = a.qd[qb[j]];
+                double* D = reinterpret_cast<double*>(q.Kt);
+                gmem(D)[i * q.ldk + qk[j]] = qrow[j] >= 0 ? sqrt(acc[j]) : 0.0;
+            }
+        }
     }
 }
 
