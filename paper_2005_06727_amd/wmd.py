@@ -180,16 +180,44 @@ def _qopts(precision=WMD_DIST_FP32, recompute_below=-1.0, log_domain=False, iter
     return _make_qopts(*args)
 
 
-def _devptr(x) -> Optional[int]:
+def _devptr(x, numel: int = 0, device: int = -1, dtype=None) -> Optional[int]:
+    """Address of a device output.  A torch tensor must be a contiguous GPU
+    tensor of ``dtype`` (float64 by default) on ``device`` holding at least
+    ``numel`` elements, since the kernels write that many; a plain int is
+    taken as a device address the caller vouches for."""
     if x is None:
         return None
     if isinstance(x, int):
         return x
     if torch is not None and isinstance(x, torch.Tensor):
-        if not x.is_cuda or x.dtype != torch.float64 or not x.is_contiguous():
-            raise ValueError("device outputs must be contiguous float64 GPU tensors")
+        want = torch.float64 if dtype is None else dtype
+        if not x.is_cuda or x.dtype != want or not x.is_contiguous():
+            raise ValueError(f"device outputs must be contiguous {want} GPU tensors")
+        if x.numel() < numel:
+            raise ValueError(f"device output holds {x.numel()} elements, the call writes {numel}")
+        if device >= 0 and x.device.index != device:
+            raise ValueError(f"device output is on cuda:{x.device.index}, the corpus on cuda:{device}")
         return x.data_ptr()
     raise TypeError("device pointer must be an int or a torch tensor")
+
+
+# (N, device) of each corpus handle, for the checks of the device-output calls
+_corpus_shape = {}
+
+
+def _corpus_nd(corpus: int) -> Tuple[int, int]:
+    nd = _corpus_shape.get(corpus)
+    if nd is None:
+        info = wmd_corpus_info_get(corpus)
+        nd = _corpus_shape[corpus] = (int(info["N"]), int(info["device"]))
+    return nd
+
+
+def _query_arrays(qids, qweights):
+    q, w = _arr(qids, np.int32), _arr(qweights, np.float32)
+    if q.shape != w.shape or q.ndim != 1:
+        raise ValueError("query ids and weights must be 1-D of equal length")
+    return q, w
 
 
 def _stream(s) -> Optional[int]:
@@ -229,6 +257,7 @@ def wmd_corpus_create(vecs, doc_ptr, word_ids, weights, device: int = -1, bf16: 
 
 
 def wmd_corpus_destroy(corpus: int) -> None:
+    _corpus_shape.pop(corpus, None)
     _lib.wmd_corpus_destroy(corpus)
 
 
@@ -240,10 +269,8 @@ def wmd_corpus_info_get(corpus: int) -> dict:
 
 def wmd_query(corpus: int, qids, qweights, lam: float, iters: int, resid: bool = False,
               **opts) -> Tuple[np.ndarray, Optional[np.ndarray]]:
-    q, w = _arr(qids, np.int32), _arr(qweights, np.float32)
-    if q.shape != w.shape or q.ndim != 1:
-        raise ValueError("query ids and weights must be 1-D of equal length")
-    N = wmd_corpus_info_get(corpus)["N"]
+    q, w = _query_arrays(qids, qweights)
+    N = _corpus_nd(corpus)[0]
     out = np.empty(N, np.float64)
     res = np.empty(N, np.float64) if resid else None
     o = _qopts(**opts)
@@ -254,15 +281,19 @@ def wmd_query(corpus: int, qids, qweights, lam: float, iters: int, resid: bool =
 
 def wmd_query_async(corpus: int, qids, qweights, lam: float, iters: int, dev_dist, dev_resid=None,
                     stream=None, **opts) -> None:
-    q, w = _arr(qids, np.int32), _arr(qweights, np.float32)
+    q, w = _query_arrays(qids, qweights)
+    N, dev = _corpus_nd(corpus)
     o = _qopts(**opts)
     _check(_lib.wmd_query_async(corpus, _ptr(q, C.c_int32), _ptr(w, C.c_float), q.size, float(lam),
-                                int(iters), C.byref(o), _devptr(dev_dist), _devptr(dev_resid),
+                                int(iters), C.byref(o), _devptr(dev_dist, N, dev), _devptr(dev_resid, N, dev),
                                 _stream(stream)))
 
 
 def _batch_args(queries: Sequence[Tuple[np.ndarray, np.ndarray]], lambdas, iters):
     B = len(queries)
+    for b, (qi, qw) in enumerate(queries):
+        if np.ndim(qi) != 1 or np.shape(qi) != np.shape(qw):
+            raise ValueError(f"query {b}: ids and weights must be 1-D of equal length")
     qp = np.zeros(B + 1, np.int64)
     qp[1:] = np.cumsum([len(q[0]) for q in queries])
     ids = _arr(np.concatenate([np.asarray(q[0]) for q in queries]), np.int32)
@@ -274,7 +305,7 @@ def _batch_args(queries: Sequence[Tuple[np.ndarray, np.ndarray]], lambdas, iters
 
 def wmd_query_batch(corpus: int, queries, lambdas, iters, resid: bool = False, **opts):
     B, qp, ids, w, lam, it = _batch_args(queries, lambdas, iters)
-    N = wmd_corpus_info_get(corpus)["N"]
+    N = _corpus_nd(corpus)[0]
     out = np.empty((B, N), np.float64)
     res = np.empty((B, N), np.float64) if resid else None
     o = _qopts(**opts)
@@ -287,19 +318,19 @@ def wmd_query_batch(corpus: int, queries, lambdas, iters, resid: bool = False, *
 def wmd_query_batch_async(corpus: int, queries, lambdas, iters, dev_dist, dev_resid=None, stream=None,
                           **opts) -> None:
     B, qp, ids, w, lam, it = _batch_args(queries, lambdas, iters)
+    N, dev = _corpus_nd(corpus)
     o = _qopts(**opts)
     _check(_lib.wmd_query_batch_async(corpus, B, _ptr(qp, C.c_int64), _ptr(ids, C.c_int32),
                                       _ptr(w, C.c_float), _ptr(lam, C.c_float), _ptr(it, C.c_int32),
-                                      C.byref(o), _devptr(dev_dist), _devptr(dev_resid), _stream(stream)))
+                                      C.byref(o), _devptr(dev_dist, B * N, dev), _devptr(dev_resid, B * N, dev),
+                                      _stream(stream)))
 
 
 def wmd_query_adaptive(corpus: int, qids, qweights, lam: float, max_iters: int, tol: float, resid: bool = False,
                        **opts):
     """Convergence-checked query: (distances, residuals or None, x updates per document)."""
-    q, w = _arr(qids, np.int32), _arr(qweights, np.float32)
-    if q.shape != w.shape or q.ndim != 1:
-        raise ValueError("query ids and weights must be 1-D of equal length")
-    N = wmd_corpus_info_get(corpus)["N"]
+    q, w = _query_arrays(qids, qweights)
+    N = _corpus_nd(corpus)[0]
     out = np.empty(N, np.float64)
     res = np.empty(N, np.float64) if resid else None
     its = np.empty(N, np.int32)
@@ -315,9 +346,7 @@ WMD_MAX_TOPK = 2048
 
 def wmd_query_topk(corpus: int, qids, qweights, lam: float, iters: int, k: int, **opts):
     """(indices, distances) of the k nearest documents, ascending by (distance, index)."""
-    q, w = _arr(qids, np.int32), _arr(qweights, np.float32)
-    if q.shape != w.shape or q.ndim != 1:
-        raise ValueError("query ids and weights must be 1-D of equal length")
+    q, w = _query_arrays(qids, qweights)
     idx = np.empty(max(int(k), 0), np.int32)
     dist = np.empty(max(int(k), 0), np.float64)
     o = _qopts(**opts)
@@ -328,14 +357,14 @@ def wmd_query_topk(corpus: int, qids, qweights, lam: float, iters: int, k: int, 
 
 def wmd_query_topk_async(corpus: int, qids, qweights, lam: float, iters: int, k: int, dev_idx, dev_dist,
                          stream=None, **opts) -> None:
-    q, w = _arr(qids, np.int32), _arr(qweights, np.float32)
+    q, w = _query_arrays(qids, qweights)
+    dev = _corpus_nd(corpus)[1]
     o = _qopts(**opts)
-    if torch is not None and isinstance(dev_idx, torch.Tensor):
-        if not dev_idx.is_cuda or dev_idx.dtype != torch.int32 or not dev_idx.is_contiguous():
-            raise ValueError("dev_idx must be a contiguous int32 GPU tensor")
-        dev_idx = dev_idx.data_ptr()
+    kk = max(int(k), 0)
+    idx_p = _devptr(dev_idx, kk, dev, torch.int32 if torch is not None else None)
     _check(_lib.wmd_query_topk_async(corpus, _ptr(q, C.c_int32), _ptr(w, C.c_float), q.size, float(lam),
-                                     int(iters), C.byref(o), int(k), dev_idx, _devptr(dev_dist), _stream(stream)))
+                                     int(iters), C.byref(o), int(k), idx_p, _devptr(dev_dist, kk, dev),
+                                     _stream(stream)))
 
 
 def wmd_set_timing(corpus: int, every) -> None:
@@ -376,9 +405,7 @@ def wmd_server_create(corpus: int, hbm_budget_bytes: Optional[int] = None, max_b
 
 
 def wmd_server_submit(server: int, qids, qweights, lam: float, iters: int) -> int:
-    q, w = _arr(qids, np.int32), _arr(qweights, np.float32)
-    if q.shape != w.shape or q.ndim != 1:
-        raise ValueError("query ids and weights must be 1-D of equal length")
+    q, w = _query_arrays(qids, qweights)
     t = _lib.wmd_server_submit(server, _ptr(q, C.c_int32), _ptr(w, C.c_float), q.size, float(lam), int(iters))
     if t < 0:
         raise WmdError(int(t), wmd_last_error())
