@@ -95,9 +95,11 @@ typedef struct wmd_query_options {
                                  FP32 accuracy bar holds at any lambda.  Needs precision
                                  WMD_DIST_FP32, tol = 0, iters_per_launch = 0, tile = -1
                                  and log_domain = 0 (WMD_EINVAL otherwise).  Limits:
-                                 32 * (embedding row + 4) floats and 16 (v_r + longest
-                                 document) + 4 (longest document) bytes of LDS, each at
-                                 most 160 KB (WMD_EINVAL beyond). */
+                                 8 * (embedding row + 4) floats (the distance kernel's
+                                 staged query rows) and 16 (v_r + longest document) +
+                                 4 (longest document + 1) bytes (the iteration's
+                                 vectors) of LDS, each at most 160 KB (WMD_EINVAL
+                                 beyond). */
 } wmd_query_options;
 
 typedef struct wmd_corpus_info {
@@ -272,19 +274,23 @@ int wmd_timing_get(wmd_corpus* corpus, wmd_timing* out);
  * of queries).
  *
  * A server owns a worker thread, `max_inflight` HIP streams and one device
- * workspace per stream, carved from `hbm_budget_bytes` (each stream gets an
- * equal share, allocated at creation).  Submitted queries wait in FIFO order;
+ * allocation of `hbm_budget_bytes`.  Submitted queries wait in FIFO order;
  * whenever a stream is free the worker launches the longest FIFO prefix (at
  * most `max_batch` queries and `max_batch_words` query words) whose workspace
- * fits that stream's share, so
- * batches admitted while others run overlap on the device.  Every query's
- * result is bitwise the one wmd_query returns for it with the same options:
- * a document's computation does not depend on the rest of the batch.
+ * fits the largest free range of the budget, and the batch's bytes return to
+ * the budget when it completes.  So batches admitted while others run
+ * overlap on the device, and a query waits only while the budget is in use
+ * by running batches (the head of the queue is never overtaken).  The worker
+ * polls the running batches' completion, keeping one host core busy while
+ * any batch is on the device.  Every query's result is bitwise the one
+ * wmd_query returns for it with the same options: a document's computation
+ * does not depend on the rest of the batch.
  */
 typedef struct wmd_server wmd_server;
 
 typedef struct wmd_server_options {
-    int64_t hbm_budget_bytes;  /* device memory of all stream workspaces together (> 0) */
+    int64_t hbm_budget_bytes;  /* device memory for the workspaces of all running batches
+                                  together (>= 256), allocated once at creation */
     int32_t max_batch;         /* queries per device batch (>= 1) */
     int32_t max_inflight;      /* concurrent batches, one stream each (1..16) */
     int32_t want_resid;        /* also keep the FP64 row-marginal residuals */
@@ -305,7 +311,7 @@ typedef struct wmd_server_stats {
     double queries_per_s;      /* completed / (last completion - first submission) */
     double doc_iters_per_s;    /* sum over completed queries of N * iters, per second */
     double mean_batch;         /* queries per launched batch */
-    int64_t workspace_bytes;   /* device memory held by the server */
+    int64_t workspace_bytes;   /* device memory held by the server (the budget) */
 } wmd_server_stats;
 
 /* Defaults: 4 GiB budget, batches of 16 and at most 512 query words, 2
@@ -313,28 +319,36 @@ typedef struct wmd_server_stats {
 void wmd_server_options_init(wmd_server_options* opt);
 
 /* Create a server on `corpus` (which must outlive it).  Errors: WMD_EINVAL for
- * bad options (budget <= 0, max_batch < 1, max_inflight outside 1..16,
+ * bad options (budget < 256, max_batch < 1, max_inflight outside 1..16,
  * invalid query options, BF16 without BF16 corpus copies), WMD_ENOMEM,
  * WMD_EDEVICE. */
 int wmd_server_create(wmd_corpus* corpus, const wmd_server_options* opt, wmd_server** out);
 
 /* Queue one query (arguments as wmd_query; host arrays copied before return).
  * Returns a ticket >= 0, or WMD_EINVAL for an invalid query, WMD_ENOMEM when
- * the query alone does not fit one stream's share of the budget,
+ * the query's workspace alone is larger than the whole budget (any smaller
+ * query is admitted once running batches leave room for it),
  * WMD_ESHUTDOWN while the server is being destroyed. */
 int64_t wmd_server_submit(wmd_server* server, const int32_t* qids, const float* qweights, int32_t n,
                           float lambda, int32_t iters);
 
 /* Wait up to timeout_us (< 0: forever) for a ticket; on success write N
  * distances (and N residuals when requested at creation and out_resid is
- * non-null) and forget the ticket.  WMD_ETIMEDOUT keeps the ticket;
- * WMD_ENOTFOUND for an unknown or collected ticket; a device error of the
- * ticket's batch is returned as WMD_EDEVICE. */
+ * non-null) and forget the ticket.  Any thread may wait on any ticket, one
+ * waiter per ticket at a time.  WMD_ETIMEDOUT keeps the ticket;
+ * WMD_ENOTFOUND for an unknown or collected ticket; WMD_EINVAL while another
+ * thread waits on the same ticket; a device error of the ticket's batch is
+ * returned as WMD_EDEVICE. */
 int wmd_server_wait(wmd_server* server, int64_t ticket, double* out_dist, double* out_resid,
                     int64_t timeout_us);
 
-/* Counters and latency percentiles since creation. */
+/* Counters and latency percentiles since creation or the last reset. */
 int wmd_server_stats_get(wmd_server* server, wmd_server_stats* out);
+
+/* Restart the statistics (e.g. after a warm-up): completed queries and
+ * latencies are forgotten; queries still queued or running count as
+ * submitted from now. */
+int wmd_server_stats_reset(wmd_server* server);
 
 /* Finish every queued and running query, then release the server.  Results
  * not collected by then are dropped.  NULL is a no-op. */

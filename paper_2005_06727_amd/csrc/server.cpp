@@ -1,6 +1,13 @@
 // Continuous-batching server: a worker thread admits queued queries into
-// batches as streams and their workspace shares free up, so batches overlap
-// on the device; results and latency statistics are kept per ticket.
+// batches as streams and device memory free up, so batches overlap on the
+// device; results and latency statistics are kept per ticket.
+//
+// Memory: one device allocation of the whole HBM budget, carved per batch by
+// a first-fit pool (byte accounting: a batch is admitted when its workspace
+// fits the largest free range, and its bytes return to the pool when it
+// completes).  Completion: the worker polls each running batch's event
+// (cheaper and quicker than a host callback), so it keeps one host core busy
+// while batches are in flight and sleeps on a condition variable otherwise.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -14,6 +21,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "pool.h"
 #include "wmd_corpus.h"
 
 using namespace wmd;
@@ -23,23 +31,22 @@ namespace {
 
 struct Ticket {
     PlannedQuery q;
+    size_t bytes = 0;                // device workspace of this query alone
     Clock::time_point t_submit, t_done;
     std::vector<double> dist, resid;
     int status = WMD_OK;
-    bool done = false;
+    std::atomic<bool> done{false};   // set under the server lock, read without it by its waiter
+    bool waited = false;             // a thread is in wmd_server_wait on it
 };
 
 struct Slot {
     hipStream_t stream = nullptr;
-    char* base = nullptr;       // this stream's share of the budget
-    size_t cap = 0;
-    Workspace w;
+    Workspace w;                     // carved from the pool per batch; pinned output and staging own
     Staging st;
     bool busy = false;
-    std::atomic<bool> finished{false};
-    std::vector<int64_t> ids;   // tickets of the running batch
+    size_t off = 0, bytes = 0;       // the running batch's pool range
+    std::vector<int64_t> ids;        // tickets of the running batch
     int status = WMD_OK;
-    wmd_server* server = nullptr;
 };
 
 }  // namespace
@@ -48,12 +55,16 @@ struct wmd_server {
     wmd_corpus* corpus = nullptr;
     wmd_server_options opt{};
     std::mutex mu;
-    std::condition_variable cv_work;   // worker: submissions, completions, shutdown
+    std::condition_variable cv_work;   // worker: submissions, shutdown
     std::condition_variable cv_done;   // waiters: finished tickets
     std::deque<int64_t> pending;
+    // node-based: a Ticket's address stays valid while other tickets are
+    // inserted or erased (only its own waiter erases it)
     std::unordered_map<int64_t, Ticket> tickets;
     int64_t next_id = 0;
     bool stop = false;
+    char* base = nullptr;              // the budget, one device allocation
+    RegionPool pool;
     std::vector<Slot*> slots;
     std::thread worker;
     // statistics
@@ -66,39 +77,24 @@ struct wmd_server {
 
 namespace {
 
-void on_batch_done(void* p) {
-    // HIP host callback: no HIP calls here, just flag and wake the worker
-    Slot* sl = static_cast<Slot*>(p);
-    wmd_server* S = sl->server;
-    {
-        std::lock_guard<std::mutex> lk(S->mu);
-        sl->finished.store(true);
-    }
-    S->cv_work.notify_all();
-}
-
-// Enqueue one batch on its slot's stream (worker thread, without the server lock).
-int launch_batch(wmd_server* S, Slot* sl, const std::vector<PlannedQuery>& qs) {
-    const bool resid = S->opt.want_resid != 0;
-    const Layout L = make_layout(S->corpus, qs, S->opt.query, resid, true);
-    if (L.device_bytes() > sl->cap) return fail(WMD_ENOMEM, "server: batch exceeds the stream's budget share");
-    carve_workspace(sl->w, sl->base, L);
+// Enqueue one batch on its slot's stream, in its pool range (worker thread,
+// without the server lock).
+int launch_batch(wmd_server* S, Slot* sl, const std::vector<PlannedQuery>& qs, const Layout& L) {
+    carve_workspace(sl->w, S->base + sl->off, L);
     double dummy = 0.0;
+    const bool resid = S->opt.want_resid != 0;
     int rc = enqueue_queries(S->corpus, qs, S->opt.query, &dummy, resid ? &dummy : nullptr, sl->stream, true,
                              sl->w, sl->st, false);
     if (rc) return rc;
     hipError_t e;
-    const size_t bytes = L.obytes;
-    if ((e = hipMemcpyAsync(sl->w.h_out, sl->w.out, bytes, hipMemcpyDeviceToHost, sl->stream)) != hipSuccess)
+    if ((e = hipMemcpyAsync(sl->w.h_out, sl->w.out, L.obytes, hipMemcpyDeviceToHost, sl->stream)) != hipSuccess)
         return hip_fail(e, "server: download results");
     if ((e = hipEventRecord(sl->w.done, sl->stream)) != hipSuccess) return hip_fail(e, "server: record");
-    if ((e = hipLaunchHostFunc(sl->stream, on_batch_done, sl)) != hipSuccess)
-        return hip_fail(e, "server: completion callback");
     return WMD_OK;
 }
 
-// Hand a finished batch's results to its tickets (worker thread, lock held on
-// entry and exit; the copies run unlocked).
+// Hand a finished batch's results to its tickets and return its memory
+// (worker thread, lock held on entry and exit; the copies run unlocked).
 void complete_batch(wmd_server* S, Slot* sl, std::unique_lock<std::mutex>& lk) {
     const int64_t N = S->corpus->dc.N;
     const size_t B = sl->ids.size();
@@ -107,7 +103,6 @@ void complete_batch(wmd_server* S, Slot* sl, std::unique_lock<std::mutex>& lk) {
     for (size_t b = 0; b < B; ++b) ts[b] = &S->tickets.at(sl->ids[b]);
     int status = sl->status;
     lk.unlock();
-    // the callback ran after the download; this also surfaces a device error of the batch
     if (status == WMD_OK && hipEventSynchronize(sl->w.done) != hipSuccess) status = WMD_EDEVICE;
     if (status == WMD_OK) {
         for (size_t b = 0; b < B; ++b) {
@@ -120,8 +115,8 @@ void complete_batch(wmd_server* S, Slot* sl, std::unique_lock<std::mutex>& lk) {
     for (size_t b = 0; b < B; ++b) {
         Ticket* t = ts[b];
         t->status = status;
-        t->done = true;
         t->t_done = now;
+        t->done.store(true, std::memory_order_release);
         if (status == WMD_OK) {
             S->completed += 1;
             S->doc_iters += (double)N * t->q.iters;
@@ -129,10 +124,19 @@ void complete_batch(wmd_server* S, Slot* sl, std::unique_lock<std::mutex>& lk) {
         }
     }
     S->t_last = now;
+    S->pool.release(sl->off, sl->bytes);
     sl->ids.clear();
     sl->busy = false;
-    sl->finished.store(false);
+    sl->bytes = 0;
     S->cv_done.notify_all();
+}
+
+// Whether a running batch has finished (or failed) on the device.
+bool batch_finished(Slot* sl) {
+    const hipError_t e = hipEventQuery(sl->w.done);
+    if (e == hipErrorNotReady) return false;
+    if (e != hipSuccess && sl->status == WMD_OK) sl->status = WMD_EDEVICE;
+    return true;
 }
 
 void worker_main(wmd_server* S) {
@@ -140,10 +144,11 @@ void worker_main(wmd_server* S) {
     const bool resid = S->opt.want_resid != 0;
     std::unique_lock<std::mutex> lk(S->mu);
     for (;;) {
-        for (Slot* sl : S->slots)
-            if (sl->busy && sl->finished.load()) complete_batch(S, sl, lk);
         bool any_busy = false;
-        for (Slot* sl : S->slots) any_busy = any_busy || sl->busy;
+        for (Slot* sl : S->slots) {
+            if (sl->busy && batch_finished(sl)) complete_batch(S, sl, lk);
+            any_busy = any_busy || sl->busy;
+        }
         if (S->stop && S->pending.empty() && !any_busy) break;
 
         bool launched = false;
@@ -158,52 +163,59 @@ void worker_main(wmd_server* S) {
                     break;
                 }
             }
-            // the longest FIFO prefix that fits this stream's share
+            // the longest FIFO prefix whose workspace fits the largest free
+            // range of the budget; the head waits (no overtaking) when even it
+            // does not fit until running batches return their memory
+            const size_t room = S->pool.largest_free();
             std::vector<PlannedQuery> qs;
-            std::vector<int64_t> ids;
             int64_t words = 0;
-            while (!S->pending.empty() && (int)ids.size() < S->opt.max_batch) {
-                const PlannedQuery& nq = S->tickets.at(S->pending.front()).q;
-                if (!ids.empty() && S->opt.max_batch_words > 0 && words + nq.m > S->opt.max_batch_words) break;
-                qs.push_back(nq);
-                if (make_layout(S->corpus, qs, S->opt.query, resid, true).device_bytes() > sl->cap) {
+            Layout L;
+            size_t n_take = 0;
+            while (n_take < S->pending.size() && (int)n_take < S->opt.max_batch) {
+                const Ticket& t = S->tickets.at(S->pending[n_take]);
+                if (n_take > 0 && S->opt.max_batch_words > 0 && words + t.q.m > S->opt.max_batch_words) break;
+                if (t.bytes > room) break;
+                qs.push_back(t.q);
+                const Layout L2 = make_layout(S->corpus, qs, S->opt.query, resid, true);
+                if (RegionPool::rounded(L2.device_bytes()) > room) {
                     qs.pop_back();
                     break;
                 }
-                words += nq.m;
-                ids.push_back(S->pending.front());
-                S->pending.pop_front();
+                L = L2;
+                words += t.q.m;
+                ++n_take;
             }
-            if (ids.empty()) {   // cannot happen: submit rejects queries larger than a share
-                const int64_t id = S->pending.front();
-                S->pending.pop_front();
-                Ticket& t = S->tickets.at(id);
-                t.status = WMD_ENOMEM;
-                t.done = true;
-                S->cv_done.notify_all();
-                continue;
-            }
+            if (n_take == 0) break;
+            size_t off = 0;
+            const size_t bytes = L.device_bytes();
+            if (!S->pool.alloc(bytes, &off)) break;   // cannot happen: bytes <= room
             sl->busy = true;
-            sl->finished.store(false);
-            sl->ids = ids;
+            sl->off = off;
+            sl->bytes = bytes;
+            sl->ids.assign(S->pending.begin(), S->pending.begin() + (std::ptrdiff_t)n_take);
+            S->pending.erase(S->pending.begin(), S->pending.begin() + (std::ptrdiff_t)n_take);
             sl->status = WMD_OK;
             S->batches += 1;
-            S->batched_queries += (int64_t)ids.size();
+            S->batched_queries += (int64_t)n_take;
             lk.unlock();
-            const int rc = launch_batch(S, sl, qs);
+            const int rc = launch_batch(S, sl, qs, L);
             if (rc != WMD_OK) (void)hipStreamSynchronize(sl->stream);   // drain what was enqueued
             lk.lock();
             if (rc != WMD_OK) {
-                // no completion callback was enqueued: fail the batch's tickets now
                 sl->status = rc;
                 complete_batch(S, sl, lk);
             }
             launched = true;
+            any_busy = true;
         }
         if (launched) continue;
-        if (any_busy || deadline != Clock::time_point::max()) {
-            const Clock::time_point until = std::min(deadline, Clock::now() + std::chrono::milliseconds(5));
-            S->cv_work.wait_until(lk, until);
+        if (any_busy) {
+            // poll the running batches; a submission needs no wake-up here
+            lk.unlock();
+            std::this_thread::yield();
+            lk.lock();
+        } else if (deadline != Clock::time_point::max()) {
+            S->cv_work.wait_until(lk, deadline);
         } else {
             S->cv_work.wait(lk, [&] { return S->stop || !S->pending.empty(); });
         }
@@ -215,12 +227,30 @@ void server_free(wmd_server* S) {
         if (sl->stream) (void)hipStreamSynchronize(sl->stream);
         free_workspace(sl->w);
         free_staging(sl->st);
-        if (sl->base) (void)hipFree(sl->base);
         if (sl->stream) (void)hipStreamDestroy(sl->stream);
         delete sl;
     }
     S->slots.clear();
+    if (S->base) (void)hipFree(S->base);
     delete S;
+}
+
+// Pinned host memory a stream slot needs for its usual batches, taken at
+// creation so that no batch pays for it: the result download of max_batch
+// queries and the staging ring for parameter blocks of up to 64 KB.
+int prealloc_slot_host(wmd_server* S, Slot* sl) {
+    const size_t out_bytes =
+        sizeof(double) * (size_t)S->opt.max_batch * (size_t)S->corpus->dc.N * (S->opt.want_resid ? 2 : 1);
+    hipError_t e;
+    if ((e = hipHostMalloc(reinterpret_cast<void**>(&sl->w.h_out), out_bytes, hipHostMallocDefault)) != hipSuccess)
+        return hip_fail(e, "server: pinned results");
+    sl->w.hocap = out_bytes;
+    const size_t stage = 64 * 1024;
+    for (int j = 0; j < Staging::kSlots; ++j)
+        if ((e = hipHostMalloc(reinterpret_cast<void**>(&sl->st.h[j]), stage, hipHostMallocDefault)) != hipSuccess)
+            return hip_fail(e, "server: pinned staging");
+    sl->st.cap = stage;
+    return WMD_OK;
 }
 
 }  // namespace
@@ -243,7 +273,8 @@ int wmd_server_create(wmd_corpus* corpus, const wmd_server_options* opt_in, wmd_
     wmd_server_options opt;
     wmd_server_options_init(&opt);
     if (opt_in) opt = *opt_in;
-    if (opt.hbm_budget_bytes <= 0) return fail(WMD_EINVAL, "server: hbm_budget_bytes must be > 0");
+    if (opt.hbm_budget_bytes < (int64_t)RegionPool::kAlign)
+        return fail(WMD_EINVAL, "server: hbm_budget_bytes must be at least %zu", RegionPool::kAlign);
     if (opt.max_batch < 1) return fail(WMD_EINVAL, "server: max_batch must be >= 1");
     if (opt.max_inflight < 1 || opt.max_inflight > 16) return fail(WMD_EINVAL, "server: max_inflight outside 1..16");
     if (opt.batch_wait_us < 0) return fail(WMD_EINVAL, "server: batch_wait_us < 0");
@@ -261,15 +292,18 @@ int wmd_server_create(wmd_corpus* corpus, const wmd_server_options* opt_in, wmd_
     wmd_server* S = new wmd_server();
     S->corpus = corpus;
     S->opt = opt;
-    const size_t share = ((size_t)opt.hbm_budget_bytes / (size_t)opt.max_inflight) / 256 * 256;
+    S->pool.reset((size_t)opt.hbm_budget_bytes);
     hipError_t e;
+    if ((e = hipMalloc(reinterpret_cast<void**>(&S->base), S->pool.capacity())) != hipSuccess) {
+        const int code = hip_fail(e, "server: device budget");
+        S->base = nullptr;
+        server_free(S);
+        return code;
+    }
     for (int i = 0; i < opt.max_inflight; ++i) {
         Slot* sl = new Slot();
-        sl->server = S;
         S->slots.push_back(sl);
-        sl->cap = share;
         if ((e = hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking)) != hipSuccess ||
-            (e = hipMalloc(reinterpret_cast<void**>(&sl->base), std::max<size_t>(share, 256))) != hipSuccess ||
             (e = hipEventCreateWithFlags(&sl->w.done, hipEventDisableTiming)) != hipSuccess) {
             const int code = hip_fail(e, "server: stream resources");
             server_free(S);
@@ -281,6 +315,10 @@ int wmd_server_create(wmd_corpus* corpus, const wmd_server_options* opt_in, wmd_
                 server_free(S);
                 return code;
             }
+        if ((rc = prealloc_slot_host(S, sl)) != WMD_OK) {
+            server_free(S);
+            return rc;
+        }
     }
     S->worker = std::thread(worker_main, S);
     *out = S;
@@ -295,14 +333,15 @@ int64_t wmd_server_submit(wmd_server* S, const int32_t* qids, const float* qweig
     if (rc) return rc;
     const std::vector<PlannedQuery> one{q};
     const size_t need = make_layout(S->corpus, one, S->opt.query, S->opt.want_resid != 0, true).device_bytes();
-    if (need > S->slots[0]->cap)
-        return fail(WMD_ENOMEM, "server: query needs %zu device bytes, one stream's share is %zu", need,
-                    S->slots[0]->cap);
+    if (RegionPool::rounded(need) > S->pool.capacity())
+        return fail(WMD_ENOMEM, "server: query needs %zu device bytes, the whole budget is %zu", need,
+                    S->pool.capacity());
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->stop) return fail(WMD_ESHUTDOWN, "server: shutting down");
     const int64_t id = S->next_id++;
     Ticket& t = S->tickets[id];
     t.q = std::move(q);
+    t.bytes = RegionPool::rounded(need);
     t.t_submit = Clock::now();
     if (!S->have_first) {
         S->have_first = true;
@@ -316,21 +355,38 @@ int64_t wmd_server_submit(wmd_server* S, const int32_t* qids, const float* qweig
 
 int wmd_server_wait(wmd_server* S, int64_t ticket, double* out_dist, double* out_resid, int64_t timeout_us) {
     if (!S || !out_dist) return fail(WMD_EINVAL, "server: null handle or output");
+    Ticket* t = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        auto it = S->tickets.find(ticket);
+        if (it == S->tickets.end()) return fail(WMD_ENOTFOUND, "server: unknown ticket %lld", (long long)ticket);
+        t = &it->second;   // stays valid: only this waiter erases it
+        if (t->waited) return fail(WMD_EINVAL, "server: ticket %lld already has a waiter", (long long)ticket);
+        t->waited = true;
+    }
+    // spin briefly (results of short queries arrive within microseconds of
+    // the device finishing), then sleep on the condition variable
+    const Clock::time_point t0 = Clock::now();
+    const Clock::time_point spin_until = t0 + std::chrono::microseconds(2000);
+    while (!t->done.load(std::memory_order_acquire) && Clock::now() < spin_until) {
+        if (timeout_us >= 0 && Clock::now() - t0 >= std::chrono::microseconds(timeout_us)) break;
+        std::this_thread::yield();
+    }
     std::unique_lock<std::mutex> lk(S->mu);
-    auto it = S->tickets.find(ticket);
-    if (it == S->tickets.end()) return fail(WMD_ENOTFOUND, "server: unknown ticket %lld", (long long)ticket);
-    auto ready = [&] { return it->second.done; };
+    auto ready = [&] { return t->done.load(std::memory_order_acquire); };
     if (timeout_us < 0) {
         S->cv_done.wait(lk, ready);
-    } else if (!S->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready)) {
+    } else if (!S->cv_done.wait_until(lk, t0 + std::chrono::microseconds(timeout_us), ready)) {
+        t->waited = false;
         return fail(WMD_ETIMEDOUT, "server: ticket %lld not finished", (long long)ticket);
     }
-    Ticket t = std::move(it->second);
-    S->tickets.erase(it);
+    const int status = t->status;
+    std::vector<double> dist = std::move(t->dist), resid = std::move(t->resid);
+    S->tickets.erase(ticket);
     lk.unlock();
-    if (t.status != WMD_OK) return fail(t.status, "server: ticket %lld failed", (long long)ticket);
-    std::memcpy(out_dist, t.dist.data(), sizeof(double) * t.dist.size());
-    if (out_resid && !t.resid.empty()) std::memcpy(out_resid, t.resid.data(), sizeof(double) * t.resid.size());
+    if (status != WMD_OK) return fail(status, "server: ticket %lld failed", (long long)ticket);
+    std::memcpy(out_dist, dist.data(), sizeof(double) * dist.size());
+    if (out_resid && !resid.empty()) std::memcpy(out_resid, resid.data(), sizeof(double) * resid.size());
     return WMD_OK;
 }
 
@@ -342,7 +398,7 @@ int wmd_server_stats_get(wmd_server* S, wmd_server_stats* out) {
     out->completed = S->completed;
     out->batches = S->batches;
     out->mean_batch = S->batches ? (double)S->batched_queries / (double)S->batches : 0.0;
-    for (Slot* sl : S->slots) out->workspace_bytes += (int64_t)sl->cap;
+    out->workspace_bytes = (int64_t)S->pool.capacity();
     if (!S->latencies_ms.empty()) {
         std::vector<double> l = S->latencies_ms;
         std::sort(l.begin(), l.end());
@@ -363,6 +419,22 @@ int wmd_server_stats_get(wmd_server* S, wmd_server_stats* out) {
             out->queries_per_s = (double)S->completed / span;
             out->doc_iters_per_s = S->doc_iters / span;
         }
+    }
+    return WMD_OK;
+}
+
+int wmd_server_stats_reset(wmd_server* S) {
+    if (!S) return fail(WMD_EINVAL, "server: null handle");
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->submitted = (int64_t)S->pending.size();
+    for (Slot* sl : S->slots) S->submitted += (int64_t)sl->ids.size();
+    S->completed = S->batches = S->batched_queries = 0;
+    S->doc_iters = 0.0;
+    S->latencies_ms.clear();
+    S->have_first = false;
+    if (S->submitted > 0) {   // queries still queued or running count from now
+        S->have_first = true;
+        S->t_first = Clock::now();
     }
     return WMD_OK;
 }

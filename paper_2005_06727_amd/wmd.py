@@ -3,7 +3,9 @@
 Every function here has the name of the C entry point it calls; all the
 arithmetic runs in the library's HIP kernels.  Importing this module loads
 ``libwmd.so`` and raises ImportError when it has not been built
-(``python -m paper_2005_06727_amd.build``).
+(``python -m paper_2005_06727_amd.build``).  The environment variable
+``WMD_LIBRARY`` names another build of the same library to load instead (for
+example one whose host code is instrumented with sanitizers).
 
 torch, when importable, is imported before the library so that the process
 holds a single HIP runtime (torch ships its own copy under the same soname);
@@ -24,7 +26,7 @@ except ImportError:  # pragma: no cover - torch is part of the image
     torch = None
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libwmd.so")
+LIB_PATH = os.environ.get("WMD_LIBRARY") or os.path.join(PKG, "libwmd.so")
 HEADER = os.path.join(os.path.dirname(PKG), "include", "wmd.h")
 
 if not os.path.exists(LIB_PATH):
@@ -117,6 +119,7 @@ _sig("wmd_server_create", C.c_int, _P, C.POINTER(wmd_server_options), C.POINTER(
 _sig("wmd_server_submit", C.c_int64, _P, _i32p, _f32p, C.c_int32, C.c_float, C.c_int32)
 _sig("wmd_server_wait", C.c_int, _P, C.c_int64, _f64p, _f64p, C.c_int64)
 _sig("wmd_server_stats_get", C.c_int, _P, C.POINTER(wmd_server_stats))
+_sig("wmd_server_stats_reset", C.c_int, _P)
 _sig("wmd_server_destroy", None, _P)
 
 
@@ -426,6 +429,10 @@ def wmd_server_stats_get(server: int) -> dict:
     return {f: getattr(st, f) for f, _ in st._fields_}
 
 
+def wmd_server_stats_reset(server: int) -> None:
+    _check(_lib.wmd_server_stats_reset(server))
+
+
 def wmd_server_destroy(server: int) -> None:
     _lib.wmd_server_destroy(server)
 
@@ -484,6 +491,9 @@ class Server:
 
     def stats(self) -> dict:
         return wmd_server_stats_get(self.handle)
+
+    def reset_stats(self) -> None:
+        wmd_server_stats_reset(self.handle)
 
     def close(self):
         if getattr(self, "handle", None):

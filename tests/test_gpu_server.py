@@ -76,22 +76,103 @@ def test_mixed_lambda_and_iters(ragged, wmd):
 
 
 def test_budget_admission(ragged, wmd):
+    """Admission is byte accounting against the whole budget: a query larger
+    than budget / max_inflight but within the budget runs (it waits until the
+    budget has room); only a query larger than the whole budget is refused."""
     (vecs, ptr, ids, w), c = ragged
-    U = c.info["U"]
+    U, N = c.info["U"], c.info["N"]
     rng = np.random.default_rng(3)
-    small = (rng.choice(vecs.shape[0], 8, replace=False).astype(np.int32), np.ones(8, np.float32))
-    big = (rng.choice(vecs.shape[0], 600, replace=False).astype(np.int32), np.ones(600, np.float32))
-    # a share that holds K for ~64 query words but not 600
-    budget = 2 * (4 * U * 64 + (1 << 20))
+
+    def query(m):
+        return rng.choice(vecs.shape[0], m, replace=False).astype(np.int32), np.ones(m, np.float32)
+
+    small, mid, big = query(8), query(300), query(600)
+    # K buffer: U x ldk floats per query; the budget holds K for ~400 query words
+    budget = 4 * U * 400 + (1 << 16)
     with wmd.Server(c, hbm_budget_bytes=budget, max_inflight=2, max_batch=32) as s:
         with pytest.raises(wmd.WmdError) as e:
             s.submit(*big, 10.0, 5)
         assert e.value.code == wmd.WMD_ENOMEM
-        tickets = [s.submit(*small, 10.0, 5) for _ in range(20)]
-        ref = c.query(*small, 10.0, 5)[0]
-        for t in tickets:
-            np.testing.assert_array_equal(s.wait(t)[0], ref)
-        assert s.stats()["workspace_bytes"] <= budget
+        # mid needs more than half of the budget: it cannot share it with a
+        # second mid, but runs
+        tickets = [s.submit(*small, 10.0, 5) for _ in range(10)] + [s.submit(*mid, 10.0, 5) for _ in range(3)] + \
+                  [s.submit(*small, 10.0, 5) for _ in range(10)]
+        ref_small = c.query(*small, 10.0, 5)[0]
+        ref_mid = c.query(*mid, 10.0, 5)[0]
+        for i, t in enumerate(tickets):
+            np.testing.assert_array_equal(s.wait(t)[0], ref_mid if 10 <= i < 13 else ref_small)
+        st = s.stats()
+        assert st["completed"] == len(tickets)
+        assert st["workspace_bytes"] <= budget
+    assert 4 * U * 300 > budget // 2
+
+
+def test_concurrent_submit_and_wait(ragged, wmd):
+    """Several threads submit and wait at once (the ticket table grows while
+    others wait on it); every result equals the single call."""
+    import threading
+    (vecs, ptr, ids, w), c = ragged
+    qs = mixed_queries(vecs.shape[0], 24, seed=77, hi=60)
+    refs = [c.query(q, qw, 10.0, 6)[0] for q, qw in qs]
+    errors = []
+    with wmd.Server(c, max_inflight=3, max_batch=4) as s:
+        def worker(k):
+            try:
+                for rep in range(6):
+                    mine = [(i, s.submit(*qs[i], 10.0, 6)) for i in range(k, len(qs), 4)]
+                    for i, t in mine:
+                        np.testing.assert_array_equal(s.wait(t)[0], refs[i])
+            except Exception as ex:   # reported by the main thread
+                errors.append(ex)
+
+        # tickets submitted here are collected by another thread
+        shared = [s.submit(*qs[i], 10.0, 6) for i in range(len(qs))]
+
+        def collector():
+            try:
+                for i, t in enumerate(shared):
+                    np.testing.assert_array_equal(s.wait(t)[0], refs[i])
+            except Exception as ex:
+                errors.append(ex)
+
+        ths = [threading.Thread(target=worker, args=(k,)) for k in range(4)] + [threading.Thread(target=collector)]
+        for th in ths:
+            th.start()
+        for th in ths:
+            th.join()
+        st = s.stats()
+    assert not errors, errors[:3]
+    assert st["completed"] == st["submitted"] == len(qs) * 7
+
+
+def test_one_waiter_per_ticket(ragged, wmd):
+    """A second wait on a ticket that already has a waiter is refused; the
+    first waiter still gets the result; stats reset forgets the warm-up."""
+    import threading
+    import time
+    (vecs, ptr, ids, w), c = ragged
+    q = np.arange(7, dtype=np.int32)
+    qw = np.ones(7, np.float32)
+    ref = c.query(q, qw, 10.0, 4)[0]
+    got = {}
+    # a lone query waits up to batch_wait_us for company, so it is still pending below
+    with wmd.Server(c, batch_wait_us=400_000, max_batch=8) as s:
+        t = s.submit(q, qw, 10.0, 4)
+        th = threading.Thread(target=lambda: got.setdefault("d", s.wait(t)[0]))
+        th.start()
+        time.sleep(0.1)
+        with pytest.raises(wmd.WmdError) as e:
+            s.wait(t, timeout_us=0)
+        assert e.value.code == wmd.WMD_EINVAL
+        th.join()
+        np.testing.assert_array_equal(got["d"], ref)
+        assert s.stats()["completed"] == 1
+        s.reset_stats()
+        st = s.stats()
+        assert st["completed"] == st["submitted"] == 0 and st["latency_p50_ms"] == 0.0
+        t2 = s.submit(q, qw, 10.0, 4)
+        np.testing.assert_array_equal(s.wait(t2)[0], ref)
+        assert s.stats()["completed"] == 1
 
 
 def test_ticket_errors_and_options(ragged, wmd):
