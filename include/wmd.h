@@ -193,6 +193,33 @@ int wmd_query_async(wmd_corpus* corpus, const int32_t* qids, const float* qweigh
                     double* dev_resid, void* stream);
 
 /*
+ * wmd_query_async for callers that cannot allocate memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.  The
+ * call makes no device or pinned-host allocation: the query's whole device
+ * workspace (K block, K .* M when lambda < 0.5, row shifts, iterate, kernel
+ * parameters) lives in one fixed array of WMD_NOALLOC_SCRATCH_BYTES that
+ * each device holds from the first corpus created on it until the process
+ * ends.  Arguments, results and options as wmd_query_async (outputs are
+ * DEVICE pointers written in stream order on `stream`).
+ *
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents (nothing in it needs to start at zero): calls that may
+ * overlap on one device (different streams, or threads) race and give wrong
+ * results; order them on one stream.  Calls on different devices do not
+ * interact.
+ *
+ * Errors: as wmd_query_async, plus WMD_EINVAL when the workspace exceeds the
+ * array (about 4 U v_r bytes, U the corpus's distinct words: v_r up to
+ * 16M / U query words, half that when lambda < 0.5, which keeps K .* M too)
+ * or the kernel parameter block exceeds 8 KB (about 600 query words).
+ */
+#define WMD_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int wmd_query_noalloc(wmd_corpus* corpus, const int32_t* qids, const float* qweights,
+                      int32_t n, float lambda, int32_t iters,
+                      const wmd_query_options* opt, double* dev_dist,
+                      double* dev_resid, void* stream);
+
+/*
  * B queries against the corpus in one distance-GEMM launch and one fused
  * Sinkhorn launch per shape class (the paper's one-to-many evaluation, Sec. 3,
  * applied to many queries at once).

@@ -547,9 +547,11 @@ int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wm
         c->last_slot = slot;
         c->last_launches = launches;
     }
-    if ((e = hipEventRecord(w.done, stream)) != hipSuccess) return hip_fail(e, "query: record");
-    w.done_valid = true;
-    w.last_stream = stream;
+    if (w.done) {   // a workspace without an event (fixed scratch) orders nothing
+        if ((e = hipEventRecord(w.done, stream)) != hipSuccess) return hip_fail(e, "query: record");
+        w.done_valid = true;
+        w.last_stream = stream;
+    }
     return WMD_OK;
 }
 
@@ -678,6 +680,8 @@ int wmd_corpus_create(const float* vecs, int64_t V, int32_t dim, const int64_t* 
     if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return fail(WMD_EDEVICE, "corpus: no current HIP device");
     DeviceGuard guard(dev);
     if (!guard.ok()) return fail(WMD_EDEVICE, "corpus: cannot select HIP device %d", dev);
+    int rc_scratch = scratch_setup(dev);
+    if (rc_scratch) return rc_scratch;
 
     wmd_corpus* c = new wmd_corpus();
     DevCorpus& d = c->dc;

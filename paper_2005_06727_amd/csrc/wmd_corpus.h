@@ -140,4 +140,7 @@ void free_workspace(Workspace& w);
 void carve_workspace(Workspace& w, char* base, const Layout& L);
 void free_staging(Staging& st);
 int check_query_options(const wmd_query_options* in, wmd_query_options* out);
+// Resolve the fixed scratch array's address on device `dev` (the current
+// device), once per device; the allocation-free entry point works in it.
+int scratch_setup(int dev);
 }  // namespace wmd

@@ -102,6 +102,8 @@ _sig("wmd_query", C.c_int, _P, _i32p, _f32p, C.c_int32, C.c_float, C.c_int32,
      C.POINTER(wmd_query_options), _f64p, _f64p)
 _sig("wmd_query_async", C.c_int, _P, _i32p, _f32p, C.c_int32, C.c_float, C.c_int32,
      C.POINTER(wmd_query_options), _P, _P, _P)
+_sig("wmd_query_noalloc", C.c_int, _P, _i32p, _f32p, C.c_int32, C.c_float, C.c_int32,
+     C.POINTER(wmd_query_options), _P, _P, _P)
 _sig("wmd_query_batch", C.c_int, _P, C.c_int32, _i64p, _i32p, _f32p, _f32p, _i32p,
      C.POINTER(wmd_query_options), _f64p, _f64p)
 _sig("wmd_query_batch_async", C.c_int, _P, C.c_int32, _i64p, _i32p, _f32p, _f32p, _i32p,
@@ -290,6 +292,18 @@ def wmd_query_async(corpus: int, qids, qweights, lam: float, iters: int, dev_dis
     _check(_lib.wmd_query_async(corpus, _ptr(q, C.c_int32), _ptr(w, C.c_float), q.size, float(lam),
                                 int(iters), C.byref(o), _devptr(dev_dist, N, dev), _devptr(dev_resid, N, dev),
                                 _stream(stream)))
+
+
+def wmd_query_noalloc(corpus: int, qids, qweights, lam: float, iters: int, dev_dist, dev_resid=None,
+                      stream=None, **opts) -> None:
+    """wmd_query_async without allocation: the workspace is the library's
+    fixed per-device scratch array (calls that overlap on one device race)."""
+    q, w = _query_arrays(qids, qweights)
+    N, dev = _corpus_nd(corpus)
+    o = _qopts(**opts)
+    _check(_lib.wmd_query_noalloc(corpus, _ptr(q, C.c_int32), _ptr(w, C.c_float), q.size, float(lam),
+                                  int(iters), C.byref(o), _devptr(dev_dist, N, dev), _devptr(dev_resid, N, dev),
+                                  _stream(stream)))
 
 
 def _batch_args(queries: Sequence[Tuple[np.ndarray, np.ndarray]], lambdas, iters):
