@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -33,6 +34,18 @@ int hip_fail(hipError_t e, const char* what) {
     return fail(e == hipErrorOutOfMemory ? WMD_ENOMEM : WMD_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
+// Fault injection for tests: with WMD_TEST_FAIL_ALLOC_BYTES=X in the
+// environment, every device allocation of at least X bytes fails as if the
+// device were out of memory (read at each allocation, so a test can switch it
+// on and off around one call).
+hipError_t device_alloc(void** p, size_t bytes) {
+    if (const char* lim = std::getenv("WMD_TEST_FAIL_ALLOC_BYTES")) {
+        const unsigned long long x = std::strtoull(lim, nullptr, 10);
+        if (x > 0 && bytes >= x) return hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
+}
+
 DeviceGuard::DeviceGuard(int dev) : dev_(dev) {
     if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
     ok_ = (prev_ == dev_) || hipSetDevice(dev_) == hipSuccess;
@@ -45,7 +58,7 @@ namespace {
 
 template <typename T>
 hipError_t dalloc(T** p, size_t count) {
-    return hipMalloc(reinterpret_cast<void**>(p), std::max<size_t>(count, 1) * sizeof(T));
+    return device_alloc(reinterpret_cast<void**>(p), std::max<size_t>(count, 1) * sizeof(T));
 }
 
 template <typename T>
@@ -155,7 +168,9 @@ int plan_query(const wmd_corpus* c, const int32_t* qids, const float* qw, int32_
         out->rinv[k] = (float)(total / w[k]);
     }
     out->m = m;
-    out->ldk = (int)align_up((size_t)m, 4);
+    // K block rows start on 128-byte lines once they exceed 16 floats, so a
+    // document's row gather reads whole lines
+    out->ldk = m <= 4 ? 4 : m <= 8 ? 8 : m <= 16 ? 16 : (int)align_up((size_t)m, 32);
     out->lambda = lambda;
     out->iters = iters;
     return WMD_OK;
@@ -525,6 +540,8 @@ int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wm
             if (q1 <= q0 || d1 <= d0) return hipSuccess;
             a.qlist = dql + q0;
             a.nq = q1 - q0;
+            a.single = (a.nq == 1) ? 1 : 0;
+            a.qd = a.single ? dq + hql[q0] : dq;
             a.d_begin = d0;
             a.d_end = d1;
             int mm = 0;

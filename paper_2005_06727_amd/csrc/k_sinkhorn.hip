@@ -20,6 +20,10 @@
 //   x_k   = (1 / r_k) sum_i A[i][k] v_i  (partial over p, then reduce-scattered
 //                                         over a: each column's sum, x and u
 //                                         are formed on one owner lane)
+// One-wave teams with R <= Q pass the column partial sums and u through LDS
+// (each lane stores its partials, the owner of a column adds them in
+// row-lane order, stores u, and every lane reads its columns' u back); the
+// others use lane shuffles (permlane swaps and DPP), as do the row sums.
 // Final: u = 1/x, v = c / (A u), WMD = sum_{i,k} ((K .* M)[i][k] u_k) v_i with
 // the products and each lane's sum over its (at most 8) columns of a row in
 // FP32 and the sum beyond in FP64, where K .* M is rebuilt from the
@@ -286,7 +290,7 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
                                           const int rs, const int n, const int m, const int ldk, const int a,
                                           const int b, const int tl, const int wi, const int team, const int kb,
                                           const int it_end, const int my_end, float* s_part, double* s_red,
-                                          float* s_rho) {
+                                          float* s_rho, float* s_x) {
     constexpr int T = R * C;
     constexpr int Q4 = Q / 4;
     // The SpMM's column sums are reduce-scattered over the R lanes of a column
@@ -303,6 +307,14 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
     static_assert((1 << LC) == C && (1 << LR) == R && (1 << LQ) == Q && C >= 4, "team shape");
     const int kf = kb + (a >> ARB) * F;              // first owned column
     const bool lead = (a & ((1 << ARB) - 1)) == 0;
+    // One-wave teams with at least as many columns as row lanes exchange
+    // through LDS instead: each lane stores its Q column partial sums, the
+    // owner of a column adds the R partials of it in row-lane order, and
+    // every lane reads the Q values of u of its columns back.  s_x holds the
+    // team's R x XS partials, then C Q values of u.
+    constexpr bool XLDS = (W == 1) && (ARB == 0);
+    constexpr int XS = C * Q + 4;                    // partial-sum row stride (floats)
+    float* const s_u = s_x + R * XS;
 
     // A and every per-row / per-column vector are zero outside the document's
     // n x m block, except that a padded row holds 1 in column 0 (which every
@@ -413,9 +425,28 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
     // u = 1/x on the owned columns (uo), spread to all Q columns of the lane (u)
     float u[Q], uo[F], s[PN], v[PN], y[Q];
     auto make_u = [&](void) {
+        if constexpr (XLDS) {
 #pragma unroll
-        for (int f = 0; f < F; ++f) uo[f] = u[f] = rcp(x[f]);
-        ag_bits<LC + ARB, RSB, F>(u);
+            for (int f = 0; f < F; ++f) {
+                uo[f] = rcp(x[f]);
+                s_u[kf + f] = uo[f];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int q4 = 0; q4 < Q4; ++q4) {
+                const float4 t = *reinterpret_cast<const float4*>(s_u + kb + 4 * q4);
+                u[4 * q4 + 0] = t.x;
+                u[4 * q4 + 1] = t.y;
+                u[4 * q4 + 2] = t.z;
+                u[4 * q4 + 3] = t.w;
+            }
+        } else {
+#pragma unroll
+            for (int f = 0; f < F; ++f) uo[f] = u[f] = rcp(x[f]);
+            ag_bits<LC + ARB, RSB, F>(u);
+        }
     };
     int par = 0;
     bool done = false;
@@ -468,8 +499,32 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
             for (int q = 0; q < Q; ++q) y[q] = fmaf(A[p][q], v[p], y[q]);
         }
         __builtin_amdgcn_sched_barrier(0);
-        rs_bits<LC + ARB, RSB, Q>(y);
-        allreduce_bits<LC, ARB, F>(y);
+        if constexpr (XLDS) {
+            // the previous readers of this region (last iteration's owners)
+            // are this wave's own earlier LDS reads: in order, no wait needed
+#pragma unroll
+            for (int q4 = 0; q4 < Q4; ++q4)
+                *reinterpret_cast<float4*>(s_x + a * XS + kb + 4 * q4) =
+                    make_float4(y[4 * q4 + 0], y[4 * q4 + 1], y[4 * q4 + 2], y[4 * q4 + 3]);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            float part[R][F];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int f = 0; f < F; ++f) part[r][f] = s_x[r * XS + kf + f];
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                float t = part[0][f];
+#pragma unroll
+                for (int r = 1; r < R; ++r) t += part[r][f];
+                y[f] = t;
+            }
+        } else {
+            rs_bits<LC + ARB, RSB, Q>(y);
+            allreduce_bits<LC, ARB, F>(y);
+        }
         __builtin_amdgcn_sched_barrier(0);
     };
 
@@ -642,6 +697,9 @@ __global__ __launch_bounds__(256, (W > 1) ? 1 : (P >= 16) ? 2 : (P <= 4) ? 5 : 3
     __shared__ double s_red[(W > 1) ? TEAMS * W * 2 : 1];
     __shared__ int s_itmax[(W > 1) ? TEAMS : 1];
     __shared__ float s_rho[(W > 1) ? TEAMS * W : 1];
+    // per-team exchange region of the one-wave tiles (see sink_team)
+    constexpr int XTEAM = (W == 1 && R <= Q) ? R * (C * Q + 4) + C * Q + 4 : 1;
+    __shared__ __attribute__((aligned(16))) float s_x[(W == 1 && R <= Q) ? TEAMS * XTEAM : 1];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int team = (W == 1) ? wave * TPW + lane / T : wave / W;
@@ -657,7 +715,7 @@ __global__ __launch_bounds__(256, (W > 1) ? 1 : (P >= 16) ? 2 : (P <= 4) ? 5 : 3
     const int qi = (int)(blockIdx.x / bpq);
     const int dd = (int)(blockIdx.x % bpq) * TEAMS + team;
     const bool valid = qi < g.nq && dd < nd;
-    const int qidx = g.qlist[qi < g.nq ? qi : 0];
+    const int qidx = g.single ? 0 : g.qlist[qi < g.nq ? qi : 0];
     const int d = g.d_begin + (valid ? dd : 0);
     const QueryDev* qp = g.qd + qidx;
     const int m = valid ? qp->m : 0;
@@ -684,7 +742,8 @@ __global__ __launch_bounds__(256, (W > 1) ? 1 : (P >= 16) ? 2 : (P <= 4) ? 5 : 3
     // so the teams of a wave have similar n); uniform, SGPR
     const int pr = __builtin_amdgcn_readfirstlane(wave_max((n + R - 1) / R));
     sink_dispatch<R, C, P, Q, W, (P >= 16) ? 2 : 1, (P >= 16) ? 2 : 1>(
-        pr, g, qp, valid, d, rs, n, m, ldk, a, b, tl, wi, team, kb, it_end, my_end, s_part, s_red, s_rho);
+        pr, g, qp, valid, d, rs, n, m, ldk, a, b, tl, wi, team, kb, it_end, my_end, s_part, s_red, s_rho,
+        s_x + ((W == 1 && R <= Q) ? team * XTEAM : 0));
 }
 
 // Any size: one 256-thread block per (query, document); the K block is
@@ -696,7 +755,7 @@ __global__ __launch_bounds__(256) void k_sink_stream(SinkArgs g) {
     const int tid = threadIdx.x;
     const int64_t item = blockIdx.x;
     const int nd = g.d_end - g.d_begin;
-    const int qidx = g.qlist[item / nd];
+    const int qidx = g.single ? 0 : g.qlist[item / nd];
     const int d = g.d_begin + (int)(item % nd);
     const QueryDev* qp = g.qd + qidx;
     const int m = qp->m, ldk = qp->ldk;
@@ -821,7 +880,7 @@ __global__ __launch_bounds__(64) void k_sink_rows(SinkArgs g) {
     const int lane = threadIdx.x;
     const int64_t item = blockIdx.x;
     const int nd = g.d_end - g.d_begin;
-    const int qidx = g.qlist[item / nd];
+    const int qidx = g.single ? 0 : g.qlist[item / nd];
     const int d = g.d_begin + (int)(item % nd);
     const QueryDev* qp = g.qd + qidx;
     const int m = qp->m, ldk = qp->ldk;

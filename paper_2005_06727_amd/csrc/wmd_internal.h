@@ -75,6 +75,9 @@ struct SinkArgs {
     int32_t it_count;      // iterations in this launch (clamped to each query's iters)
     int32_t final_step;    // nonzero: run the final u/v/WMD step at the end
     const float* zpad;     // the corpus's zero block
+    // nonzero: the launch has one query whose record is qd[0]; qlist is not
+    // read, so the record's load does not wait for a load of qlist
+    int32_t single = 0;
 };
 
 // ---- launchers (return hipError_t of the launch) ----
