@@ -294,7 +294,7 @@ int wmd_server_create(wmd_corpus* corpus, const wmd_server_options* opt_in, wmd_
     S->opt = opt;
     S->pool.reset((size_t)opt.hbm_budget_bytes);
     hipError_t e;
-    if ((e = hipMalloc(reinterpret_cast<void**>(&S->base), S->pool.capacity())) != hipSuccess) {
+    if ((e = device_alloc(reinterpret_cast<void**>(&S->base), S->pool.capacity())) != hipSuccess) {
         const int code = hip_fail(e, "server: device budget");
         S->base = nullptr;
         server_free(S);

@@ -89,6 +89,8 @@ class DeviceGuard {
 
 int fail(int code, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);
+// hipMalloc behind the library's fault-injection switch (WMD_TEST_FAIL_ALLOC_BYTES)
+hipError_t device_alloc(void** p, size_t bytes);
 extern thread_local std::string g_err;
 
 }  // namespace wmd

@@ -34,7 +34,7 @@ import numpy as np
 
 __all__ = [
     "WorkloadSpec", "Workload", "SPECS", "embeddings", "zipf_cdf",
-    "corpus", "query", "loguniform_lengths", "make", "subcorpus",
+    "corpus", "query", "loguniform_lengths", "make", "subcorpus", "near_duplicates",
 ]
 
 
@@ -176,3 +176,23 @@ def subcorpus(doc_ptr: np.ndarray, word_ids: np.ndarray, weights: np.ndarray,
     sel = np.concatenate([np.arange(doc_ptr[d], doc_ptr[d + 1]) for d in docs]) \
         if docs.size else np.zeros(0, dtype=np.int64)
     return ptr, word_ids[sel].copy(), weights[sel].copy()
+
+
+def near_duplicates(vecs: np.ndarray, bases: np.ndarray, rows: np.ndarray, dists: np.ndarray,
+                    rng: np.random.Generator) -> np.ndarray:
+    """A copy of ``vecs`` in which row ``rows[i]`` is replaced by a unit vector
+    at Euclidean (chord) distance ``dists[i]`` from row ``bases[i]``: the base
+    rotated by the angle 2 asin(d / 2) towards a random direction orthogonal
+    to it, in FP64, then rounded to FP32 like every embedding.  Real
+    embedding tables hold such near-synonyms; the synthetic N(0, 1) rows do
+    not (their pairwise distances lie near sqrt(2))."""
+    out = np.array(vecs, dtype=np.float32, copy=True)
+    for b, r, d in zip(np.asarray(bases), np.asarray(rows), np.asarray(dists, dtype=np.float64)):
+        e = out[b].astype(np.float64)
+        e /= np.linalg.norm(e)
+        z = rng.standard_normal(e.size)
+        z -= (z @ e) * e
+        z /= np.linalg.norm(z)
+        th = 2.0 * np.arcsin(d / 2.0)
+        out[r] = (np.cos(th) * e + np.sin(th) * z).astype(np.float32)
+    return out

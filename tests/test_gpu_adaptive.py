@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 from oracle import sinkhorn_wmd_sparse
-from tests.test_gpu_parity import FP32_RTOL, ragged_corpus, rel_err
+from tests.test_gpu_parity import FP32_RTOL, RESID_ATOL, RESID_RTOL, ragged_corpus, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -63,7 +63,7 @@ def test_adaptive_counts_and_distances(ragged, wmd, m, tile):
     assert np.any(t < max_iters) and np.any(t > 1)
     want, wres = sinkhorn_wmd_sparse(vecs, q, qw, ptr, ids, w, lam, t.astype(np.int64))
     assert rel_err(d, want).max() <= FP32_RTOL
-    np.testing.assert_allclose(res, wres, rtol=1e-2, atol=1e-6)
+    np.testing.assert_allclose(res, wres, rtol=RESID_RTOL, atol=RESID_ATOL)
 
 
 @pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, 6, 7, 11])   # the register tiles
