@@ -70,6 +70,9 @@ def parse():
     p.add_argument("--steps", type=int, default=5000)
     p.add_argument("--warmup", type=int, default=3000)
     p.add_argument("--workload", default="c2", choices=["c1", "c2"])
+    p.add_argument("--headline-streams", type=int, default=STREAMS,
+                   help="streams the headline queries alternate over (1: every kernel runs alone, as the "
+                        "single-stream kernel trace in profiles/ is taken)")
     p.add_argument("--latency-calls", type=int, default=300)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-batch", action="store_true", help="skip the 64-query batch section")
@@ -686,10 +689,11 @@ def main():
     # consecutive queries alternate between STREAMS streams (and the library's
     # two workspace slots), so one query's distance GEMM overlaps the previous
     # query's Sinkhorn kernel
-    streams = [torch.cuda.Stream() for _ in range(STREAMS)]
+    nstr = max(1, args.headline_streams)
+    streams = [torch.cuda.Stream() for _ in range(nstr)]
     outs = [torch.empty(N, dtype=torch.float64, device="cuda") for _ in streams]
 
-    def step(i, nstreams=STREAMS):
+    def step(i, nstreams=nstr):
         j = i % nstreams
         wmd.wmd_query_async(h, q, qw, sp.lam, sp.iters, outs[j], None, streams[j])
 
@@ -793,7 +797,7 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{sp.name}: 1 query (v_r={m}) vs N={N} docs, V={sp.V}, dim={dim}, "
                                f"nnz={nnz}, U={U}, lambda={sp.lam}, {sp.iters} iterations, FP32 distances; "
-                               f"consecutive queries on {STREAMS} streams, results in device memory",
+                               f"consecutive queries on {nstr} streams, results in device memory",
                    "V": sp.V, "dim": dim, "N": N, "nnz": nnz, "U": U, "v_r": int(m), "lambda": sp.lam,
                    "iters": sp.iters, "parallelism": "single GPU"},
         "warmup_steps_run": warmed,
@@ -805,7 +809,7 @@ def main():
                       if lat.size else None),
         "roofline": roofline,
         "kernels": kernels,
-        "streams": STREAMS,
+        "streams": nstr,
         "launches_per_step": iso["launches"],
     }
     if not args.no_batch:

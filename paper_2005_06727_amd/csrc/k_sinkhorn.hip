@@ -20,8 +20,8 @@
 //   x_k   = (1 / r_k) sum_i A[i][k] v_i  (partial over p, then reduce-scattered
 //                                         over a: each column's sum, x and u
 //                                         are formed on one owner lane)
-// One-wave teams with R <= Q pass the column partial sums and u through LDS
-// (each lane stores its partials, the owner of a column adds them in
+// Teams with R <= Q and C < 16 pass the column partial sums and u through
+// LDS (each lane stores its partials, the owner of a column adds them in
 // row-lane order, stores u, and every lane reads its columns' u back); the
 // others use lane shuffles (permlane swaps and DPP), as do the row sums.
 // Final: u = 1/x, v = c / (A u), WMD = sum_{i,k} ((K .* M)[i][k] u_k) v_i with
@@ -307,14 +307,19 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
     static_assert((1 << LC) == C && (1 << LR) == R && (1 << LQ) == Q && C >= 4, "team shape");
     const int kf = kb + (a >> ARB) * F;              // first owned column
     const bool lead = (a & ((1 << ARB) - 1)) == 0;
-    // One-wave teams with at least as many columns as row lanes exchange
-    // through LDS instead: each lane stores its Q column partial sums, the
-    // owner of a column adds the R partials of it in row-lane order, and
-    // every lane reads the Q values of u of its columns back.  s_x holds the
-    // team's R x XS partials, then C Q values of u.
-    constexpr bool XLDS = (W == 1) && (ARB == 0);
+    // Teams with at least as many columns as row lanes, whose row lanes sit
+    // on the low lane bits (C < 16, where the shuffles need DPP bank moves,
+    // selects and wait states; the permlane swaps of bits 4 and 5 are cheaper
+    // than a round trip through LDS), exchange through LDS instead: each lane
+    // stores its Q column partial sums, the owner of a column adds the R
+    // partials of it in row-lane order, and every lane reads the Q values of
+    // u of its columns back.  s_x is this wave's region (each wave of a team
+    // has its own C Q columns): R x XS partials, then C Q values of u,
+    // indexed by the column within the wave (kbl, kfl).
+    constexpr bool XLDS = (ARB == 0) && (C < 16);
     constexpr int XS = C * Q + 4;                    // partial-sum row stride (floats)
     float* const s_u = s_x + R * XS;
+    const int kbl = b * Q, kfl = kbl + (a >> ARB) * F;
 
     // A and every per-row / per-column vector are zero outside the document's
     // n x m block, except that a padded row holds 1 in column 0 (which every
@@ -429,14 +434,14 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
 #pragma unroll
             for (int f = 0; f < F; ++f) {
                 uo[f] = rcp(x[f]);
-                s_u[kf + f] = uo[f];
+                s_u[kfl + f] = uo[f];
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
             for (int q4 = 0; q4 < Q4; ++q4) {
-                const float4 t = *reinterpret_cast<const float4*>(s_u + kb + 4 * q4);
+                const float4 t = *reinterpret_cast<const float4*>(s_u + kbl + 4 * q4);
                 u[4 * q4 + 0] = t.x;
                 u[4 * q4 + 1] = t.y;
                 u[4 * q4 + 2] = t.z;
@@ -504,7 +509,7 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
             // are this wave's own earlier LDS reads: in order, no wait needed
 #pragma unroll
             for (int q4 = 0; q4 < Q4; ++q4)
-                *reinterpret_cast<float4*>(s_x + a * XS + kb + 4 * q4) =
+                *reinterpret_cast<float4*>(s_x + a * XS + kbl + 4 * q4) =
                     make_float4(y[4 * q4 + 0], y[4 * q4 + 1], y[4 * q4 + 2], y[4 * q4 + 3]);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -513,7 +518,7 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
 #pragma unroll
             for (int r = 0; r < R; ++r)
 #pragma unroll
-                for (int f = 0; f < F; ++f) part[r][f] = s_x[r * XS + kf + f];
+                for (int f = 0; f < F; ++f) part[r][f] = s_x[r * XS + kfl + f];
 #pragma unroll
             for (int f = 0; f < F; ++f) {
                 float t = part[0][f];
@@ -698,8 +703,9 @@ __global__ __launch_bounds__(256, (W > 1) ? 1 : (P >= 16) ? 2 : (P <= 4) ? 5 : 3
     __shared__ int s_itmax[(W > 1) ? TEAMS : 1];
     __shared__ float s_rho[(W > 1) ? TEAMS * W : 1];
     // per-team exchange region of the one-wave tiles (see sink_team)
-    constexpr int XTEAM = (W == 1 && R <= Q) ? R * (C * Q + 4) + C * Q + 4 : 1;
-    __shared__ __attribute__((aligned(16))) float s_x[(W == 1 && R <= Q) ? TEAMS * XTEAM : 1];
+    constexpr bool XL = (R <= Q) && (C < 16);
+    constexpr int XTEAM = XL ? R * (C * Q + 4) + C * Q + 4 : 1;
+    __shared__ __attribute__((aligned(16))) float s_x[XL ? TEAMS * W * XTEAM : 1];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int team = (W == 1) ? wave * TPW + lane / T : wave / W;
@@ -743,7 +749,7 @@ __global__ __launch_bounds__(256, (W > 1) ? 1 : (P >= 16) ? 2 : (P <= 4) ? 5 : 3
     const int pr = __builtin_amdgcn_readfirstlane(wave_max((n + R - 1) / R));
     sink_dispatch<R, C, P, Q, W, (P >= 16) ? 2 : 1, (P >= 16) ? 2 : 1>(
         pr, g, qp, valid, d, rs, n, m, ldk, a, b, tl, wi, team, kb, it_end, my_end, s_part, s_red, s_rho,
-        s_x + ((W == 1 && R <= Q) ? team * XTEAM : 0));
+        s_x + (XL ? (team * W + wi) * XTEAM : 0));
 }
 
 // Any size: one 256-thread block per (query, document); the K block is
