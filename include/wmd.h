@@ -276,11 +276,14 @@ int wmd_query_topk_async(wmd_corpus* corpus, const int32_t* qids, const float* q
                          int32_t k, int32_t* dev_idx, double* dev_dist, void* stream);
 
 /*
- * Kernel timing, recorded with HIP events on the stream the kernels run on.
- * wmd_set_timing(corpus, k) with k > 0 clears the totals and records every
- * k-th query or batch call from then on (1: every call; event records cost
- * host and device time, so sparse sampling disturbs a pipeline less); 0
- * disables it.  wmd_timing_get waits for the recorded events and returns
+ * Kernel timing with HIP events on the stream the kernels run on.  A timed
+ * call launches its kernels through hipExtLaunchKernel, so each phase's pair
+ * of events holds the start of its first kernel dispatch and the end of its
+ * last (the times a kernel trace reports), not the gaps around them.
+ * wmd_set_timing(corpus, k) with k > 0 clears the totals and times every
+ * k-th query or batch call from then on (1: every call; timed launches cost
+ * some host time, so sparse sampling disturbs a pipeline less); 0 disables
+ * it.  wmd_timing_get waits for the recorded events and returns
  * milliseconds.  Errors: WMD_EINVAL for k < 0.
  */
 typedef struct wmd_timing {

@@ -334,13 +334,36 @@ static int take_staging(Staging& st, size_t bytes, int* slot_out) {
     return WMD_OK;
 }
 
+DispatchClock& dispatch_clock() {
+    thread_local DispatchClock clock;
+    return clock;
+}
+
+namespace {
+
+// Clears the calling thread's dispatch clock when it leaves scope.
+struct ClockReset {
+    ~ClockReset() { dispatch_clock() = DispatchClock{}; }
+};
+
+// End of a timed phase: a phase that launched nothing records both of its
+// events here, so its duration reads as zero.
+hipError_t close_phase(hipStream_t s) {
+    DispatchClock& k = dispatch_clock();
+    if (!k.start) return hipSuccess;
+    hipError_t e = hipEventRecord(k.start, s);
+    return e != hipSuccess ? e : hipEventRecord(k.stop, s);
+}
+
+}  // namespace
+
 // Wait for a timed call's events and add its kernel times to the totals.
 int fold_timing_slot(wmd_corpus* c, int slot) {
     hipError_t e;
     float d = 0.f, k = 0.f;
-    if ((e = hipEventSynchronize(c->ev[slot][2])) != hipSuccess) return hip_fail(e, "timing: wait");
+    if ((e = hipEventSynchronize(c->ev[slot][3])) != hipSuccess) return hip_fail(e, "timing: wait");
     if ((e = hipEventElapsedTime(&d, c->ev[slot][0], c->ev[slot][1])) != hipSuccess ||
-        (e = hipEventElapsedTime(&k, c->ev[slot][1], c->ev[slot][2])) != hipSuccess)
+        (e = hipEventElapsedTime(&k, c->ev[slot][2], c->ev[slot][3])) != hipSuccess)
         return hip_fail(e, "timing: elapsed");
     c->slot_pending[slot] = false;
     c->timed_calls += 1;
@@ -491,11 +514,12 @@ int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wm
     const int32_t* dql = reinterpret_cast<const int32_t*>(dp + off_ql);
     int launches = 0;
     int slot = -1;
+    ClockReset clock_reset;   // the dispatch clock is off again however this returns
     if (timed) {
         slot = c->next_slot;
         c->next_slot = (c->next_slot + 1) % wmd_corpus::kTimingSlots;
         if (c->slot_pending[slot] && (rc = fold_timing_slot(c, slot))) return rc;
-        (void)hipEventRecord(c->ev[slot][0], stream);
+        dispatch_clock() = DispatchClock{c->ev[slot][0], c->ev[slot][1]};
     }
     const int32_t* dqg = reinterpret_cast<const int32_t*>(dp + off_qg);
     if (opt.lse) e = launch_dist_lse(dc, dq, dqg, B, (int)sum_ldk, stream);
@@ -503,7 +527,10 @@ int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wm
     else e = launch_dist(dc, dq, dqg, B, (int)sum_ldk, bf16, opt.log_domain, w.nrow, stream);
     if (e != hipSuccess) return hip_fail(e, "query: distance kernel launch");
     ++launches;
-    if (slot >= 0) (void)hipEventRecord(c->ev[slot][1], stream);
+    if (slot >= 0) {
+        if ((e = close_phase(stream)) != hipSuccess) return hip_fail(e, "query: record");
+        dispatch_clock() = DispatchClock{c->ev[slot][2], c->ev[slot][3]};
+    }
 
     const int d_tile = (int)c->d_tile;   // sorted docs [d_tile, N) fit the register tiles
     if (opt.lse) {   // every query and document in one log-domain launch
@@ -518,6 +545,8 @@ int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wm
         a.scw = dc.scw;
         a.sdoc = dc.sdoc;
         a.zpad = dc.zpad;
+        a.pent = dc.pent;
+        a.pad_d0 = (int32_t)dc.pad_d0;
         a.it_begin = 0;
         a.it_count = max_iters;
         a.final_step = 1;
@@ -533,6 +562,8 @@ int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wm
         a.scw = dc.scw;
         a.sdoc = dc.sdoc;
         a.zpad = dc.zpad;
+        a.pent = dc.pent;
+        a.pad_d0 = (int32_t)dc.pad_d0;
         a.it_begin = it0;
         a.it_count = per_launch;
         a.final_step = (int64_t)it0 + per_launch >= max_iters ? 1 : 0;
@@ -559,7 +590,8 @@ int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wm
         if (a.final_step) break;
     }
     if (slot >= 0) {
-        (void)hipEventRecord(c->ev[slot][2], stream);
+        if ((e = close_phase(stream)) != hipSuccess) return hip_fail(e, "query: record");
+        dispatch_clock() = DispatchClock{};
         c->slot_pending[slot] = true;
         c->last_slot = slot;
         c->last_launches = launches;
@@ -612,10 +644,11 @@ static void corpus_free(wmd_corpus* c) {
     dfree(d.scw);
     dfree(d.sdoc);
     dfree(d.zpad);
+    dfree(d.pent);
     for (int sl = 0; sl < kWorkSlots; ++sl) free_workspace(c->ws[sl]);
     free_staging(c->stage);
     for (int i = 0; i < wmd_corpus::kTimingSlots; ++i)
-        for (int j = 0; j < 3; ++j)
+        for (int j = 0; j < wmd_corpus::kTimingEvents; ++j)
             if (c->ev[i][j]) (void)hipEventDestroy(c->ev[i][j]);
     if (c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
@@ -714,6 +747,8 @@ int wmd_corpus_create(const float* vecs, int64_t V, int32_t dim, const int64_t* 
     c->h_sorted_len.push_back(0);
     c->d_tile = 0;
     while (c->d_tile < N && slen[c->d_tile] > kTileMaxDoc) ++c->d_tile;
+    d.pad_d0 = c->d_tile;
+    const size_t npent = (size_t)(N - c->d_tile) * kPadDocWidth;
 
     hipError_t e = hipSuccess;
     auto bail = [&](hipError_t err, const char* what) {
@@ -730,14 +765,15 @@ int wmd_corpus_create(const float* vecs, int64_t V, int32_t dim, const int64_t* 
         if ((e = hipEventCreateWithFlags(&c->stage.ev[i], hipEventDisableTiming)) != hipSuccess)
             return bail(e, "corpus: events");
     for (int i = 0; i < wmd_corpus::kTimingSlots; ++i)
-        for (int j = 0; j < 3; ++j)
+        for (int j = 0; j < wmd_corpus::kTimingEvents; ++j)
             if ((e = hipEventCreate(&c->ev[i][j])) != hipSuccess) return bail(e, "corpus: timing events");
     const size_t ldv = (size_t)d.ldv;
     if ((e = dalloc(&d.vecs, (size_t)V * ldv)) != hipSuccess || (e = dalloc(&d.act, (size_t)U * ldv)) != hipSuccess ||
         (e = dalloc(&d.act_norm, (size_t)U)) != hipSuccess || (e = dalloc(&d.act_word, (size_t)U)) != hipSuccess ||
         (e = dalloc(&d.sptr, (size_t)N + 1)) != hipSuccess || (e = dalloc(&d.scol, (size_t)nnz)) != hipSuccess ||
         (e = dalloc(&d.scw, (size_t)nnz)) != hipSuccess || (e = dalloc(&d.sdoc, (size_t)N)) != hipSuccess ||
-        (e = dalloc(&d.zpad, (size_t)kZpadFloats)) != hipSuccess)
+        (e = dalloc(&d.zpad, (size_t)kZpadFloats)) != hipSuccess ||
+        (npent > 0 && (e = dalloc(&d.pent, npent)) != hipSuccess))
         return bail(e, "corpus: device allocation");
     if (opt.bf16) {
         if ((e = dalloc(&d.act_bf16, (size_t)U * ldv)) != hipSuccess ||
@@ -759,14 +795,16 @@ int wmd_corpus_create(const float* vecs, int64_t V, int32_t dim, const int64_t* 
         return bail(e, "corpus: upload");
     if ((e = launch_gather_rows(d.vecs, d.act_word, d.act, U, d.ldv, s)) != hipSuccess ||
         (e = launch_prep_norms(d.act, U, d.ldv, d.act_norm, s)) != hipSuccess ||
-        (e = launch_prep_docs(d.sptr, d.scw, d.scw, N, s)) != hipSuccess)
+        (e = launch_prep_docs(d.sptr, d.scw, d.scw, N, s)) != hipSuccess ||
+        (e = launch_prep_doc_pad(d.sptr, d.scol, d.scw, d.pad_d0, N, kPadDocWidth, d.pent, s)) != hipSuccess)
         return bail(e, "corpus: preparation kernels");
     if (opt.bf16 && (e = launch_prep_bf16(d.act, d.act_bf16, d.act_norm_bf16, U, d.ldv, s)) != hipSuccess)
         return bail(e, "corpus: BF16 preparation");
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return bail(e, "corpus: preparation");
     c->device_bytes = (int64_t)((V + U) * ldv * sizeof(float) + U * (sizeof(float) + sizeof(int32_t)) +
                                 (N + 1 + N) * sizeof(int32_t) + nnz * (sizeof(int32_t) + sizeof(float)) +
-                                kZpadFloats * sizeof(float) + (opt.bf16 ? U * (ldv * sizeof(uint16_t) + sizeof(float)) : 0));
+                                kZpadFloats * sizeof(float) + npent * sizeof(int2) +
+                                (opt.bf16 ? U * (ldv * sizeof(uint16_t) + sizeof(float)) : 0));
     *out = c;
     return WMD_OK;
 }
@@ -1032,7 +1070,7 @@ int wmd_set_timing(wmd_corpus* c, int32_t enable) {
     DeviceGuard guard(c->dc.device);
     for (int i = 0; i < wmd_corpus::kTimingSlots; ++i)
         if (c->slot_pending[i]) {
-            hipError_t e = hipEventSynchronize(c->ev[i][2]);
+            hipError_t e = hipEventSynchronize(c->ev[i][3]);
             if (e != hipSuccess) return hip_fail(e, "timing: wait");
             c->slot_pending[i] = false;
         }

@@ -25,6 +25,7 @@
 #include <cstring>
 
 #include "wmd_device.h"
+#include "launch.h"
 #include "wmd_internal.h"
 
 namespace wmd {
@@ -551,9 +552,9 @@ hipError_t launch_dist(const DevCorpus& c, const QueryDev* qd, const int32_t* ko
     hipError_t e;
     if (shift) {
         const int64_t n = c.U * (int64_t)B;
-        hipLaunchKernelGGL(k_fill_inf, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0, s,
-                           nrow_all, n);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = launch_kernel(k_fill_inf, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0, s,
+                               nrow_all, n)) != hipSuccess)
+            return e;
     }
     DistArgs a;
     a.act = c.act;
@@ -573,19 +574,13 @@ hipError_t launch_dist(const DevCorpus& c, const QueryDev* qd, const int32_t* ko
     const int64_t nblocks = tiles_r * a.tiles_c;
     if (nblocks > INT32_MAX) return hipErrorInvalidValue;
     a.nblocks = (int32_t)nblocks;
-    if (tc == 32) {
-        // FP32 rows are 4 * ldv bytes (a multiple of 256), BF16 rows 2 * ldv (of 128)
-        if (bf16) hipLaunchKernelGGL((k_dist<true, 32, 128>), dim3((unsigned)nblocks), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((k_dist<false, 32, 256>), dim3((unsigned)nblocks), dim3(256), 0, s, a);
-    } else {
-        if (bf16) hipLaunchKernelGGL((k_dist<true, 64, 128>), dim3((unsigned)nblocks), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((k_dist<false, 64, 128>), dim3((unsigned)nblocks), dim3(256), 0, s, a);
-    }
-    if ((e = hipGetLastError()) != hipSuccess || !shift) return e;
+    // FP32 rows are 4 * ldv bytes (a multiple of 256), BF16 rows 2 * ldv (of 128)
+    auto kern = tc == 32 ? (bf16 ? k_dist<true, 32, 128> : k_dist<false, 32, 256>)
+                         : (bf16 ? k_dist<true, 64, 128> : k_dist<false, 64, 128>);
+    if ((e = launch_kernel(kern, dim3((unsigned)nblocks), dim3(256), 0, s, a)) != hipSuccess || !shift) return e;
     const int64_t per_q = (c.U * 64 + 255) / 256;
-    hipLaunchKernelGGL(k_shift_exp, dim3((unsigned)std::min<int64_t>(per_q, 2048), (unsigned)B), dim3(256), 0, s,
-                       qd, c.U);
-    return hipGetLastError();
+    return launch_kernel(k_shift_exp, dim3((unsigned)std::min<int64_t>(per_q, 2048), (unsigned)B), dim3(256), 0, s,
+                         qd, c.U);
 }
 
 bool dist_narrow_fits(const DevCorpus& c, int bf16, int B, int ncols, size_t pbytes) {
@@ -621,16 +616,16 @@ hipError_t launch_dist_narrow(const DevCorpus& c, const QueryDev& hq, const Quer
     std::memcpy(a.blob, blob, pbytes);
     hipError_t e;
     if (hq.shift) {
-        hipLaunchKernelGGL(k_fill_inf, dim3((unsigned)std::min<int64_t>((c.U + 255) / 256, 4096)), dim3(256), 0, s,
-                           hq.nrow, c.U);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = launch_kernel(k_fill_inf, dim3((unsigned)std::min<int64_t>((c.U + 255) / 256, 4096)), dim3(256), 0,
+                               s, hq.nrow, c.U)) != hipSuccess)
+            return e;
     }
     const int nc = c.ldv * (bf16 ? 2 : 4) / 128;
     const unsigned blocks = (unsigned)((c.U + TR - 1) / TR);
-#define WMD_NARROW(K)                                                                           \
-    case K:                                                                                     \
-        if (bf16) hipLaunchKernelGGL((k_dist_narrow<true, K>), dim3(blocks), dim3(256), 0, s, a); \
-        else hipLaunchKernelGGL((k_dist_narrow<false, K>), dim3(blocks), dim3(256), 0, s, a);     \
+#define WMD_NARROW(K)                                                                        \
+    case K:                                                                                  \
+        e = launch_kernel(bf16 ? k_dist_narrow<true, K> : k_dist_narrow<false, K>, dim3(blocks), \
+                          dim3(256), 0, s, a);                                               \
         break;
     switch (nc) {
         WMD_NARROW(1) WMD_NARROW(2) WMD_NARROW(3) WMD_NARROW(4) WMD_NARROW(5) WMD_NARROW(6)
@@ -638,10 +633,9 @@ hipError_t launch_dist_narrow(const DevCorpus& c, const QueryDev& hq, const Quer
         default: return hipErrorInvalidValue;
     }
 #undef WMD_NARROW
-    if ((e = hipGetLastError()) != hipSuccess || !hq.shift) return e;
-    hipLaunchKernelGGL(k_shift_exp, dim3((unsigned)std::min<int64_t>((c.U * 32 + 255) / 256, 2048), 1u), dim3(256),
-                       0, s, qd_dev, c.U);
-    return hipGetLastError();
+    if (e != hipSuccess || !hq.shift) return e;
+    return launch_kernel(k_shift_exp, dim3((unsigned)std::min<int64_t>((c.U * 32 + 255) / 256, 2048), 1u), dim3(256),
+                         0, s, qd_dev, c.U);
 }
 
 }  // namespace wmd

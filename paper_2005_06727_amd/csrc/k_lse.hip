@@ -17,6 +17,7 @@
 // FP32.  FP32 distances would not do: lambda times their rounding error is
 // already ~1e-4 at lambda = 1000.
 #include "wmd_device.h"
+#include "launch.h"
 #include "wmd_internal.h"
 
 namespace wmd {
@@ -352,8 +353,7 @@ hipError_t launch_dist_lse(const DevCorpus& c, const QueryDev* qd, const int32_t
         if (e != hipSuccess) return e;
     }
     const dim3 grid((unsigned)((c.U + kRows - 1) / kRows), (unsigned)((ncols + kCols - 1) / kCols));
-    hipLaunchKernelGGL(k_dist_lse, grid, dim3(256), lds, s, a);
-    return hipGetLastError();
+    return launch_kernel(k_dist_lse, grid, dim3(256), (uint32_t)lds, s, a);
 }
 
 hipError_t launch_sinkhorn_lse(const SinkArgs& a, int max_m, int max_n, hipStream_t s) {
@@ -366,9 +366,8 @@ hipError_t launch_sinkhorn_lse(const SinkArgs& a, int max_m, int max_n, hipStrea
         hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    if (staged) hipLaunchKernelGGL(k_sink_lse<true>, dim3((unsigned)nitems), dim3(64), lds, s, a);
-    else hipLaunchKernelGGL(k_sink_lse<false>, dim3((unsigned)nitems), dim3(64), lds, s, a);
-    return hipGetLastError();
+    return launch_kernel(staged ? k_sink_lse<true> : k_sink_lse<false>, dim3((unsigned)nitems), dim3(64),
+                         (uint32_t)lds, s, a);
 }
 
 }  // namespace wmd

@@ -34,6 +34,7 @@
 // sum_k |u_k (A^T v)_k - r_k| of the plan's row marginal (its column marginal
 // is c by construction).
 #include "wmd_device.h"
+#include "launch.h"
 #include "wmd_internal.h"
 
 // No implicit multiply-add contraction in this file: every fused operation is
@@ -271,12 +272,6 @@ __device__ __forceinline__ double team_sum_f64(double v) {
     return v;
 }
 
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) v = max(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // added to every x update (see sink_team)
@@ -290,7 +285,7 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
                                           const int rs, const int n, const int m, const int ldk, const int a,
                                           const int b, const int tl, const int wi, const int team, const int kb,
                                           const int it_end, const int my_end, float* s_part, double* s_red,
-                                          float* s_rho, float* s_x) {
+                                          float* s_rho, float* s_x, const int2 (&pe)[(W == 1) ? P : 1]) {
     constexpr int T = R * C;
     constexpr int Q4 = Q / 4;
     // The SpMM's column sums are reduce-scattered over the R lanes of a column
@@ -334,20 +329,17 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
     float cval[PN];
     float A[PN][Q];
     if constexpr (W == 1) {
-        // Branch-free loads, all in flight at once (a branch per row makes the
-        // compiler wait for each row's loads before issuing the next): the
-        // indices and weights of the lane's rows first, then the rows of Kt.
-        // A row beyond the document reads index 0 (present: every document has
-        // a word) and its Kt values from the zero block, whose first four
-        // values are (1, 0, 0, 0); a column group beyond m reads zeros there
-        // too.  Choosing the address instead of the loaded value keeps the
-        // loads' destinations in A (no second set of registers).
+        // Branch-free loads of the rows of Kt, all in flight at once (a branch
+        // per row makes the compiler wait for each row's loads before issuing
+        // the next); the row entries came with the document's rank.  A row
+        // beyond the document reads its Kt values from the zero block, whose
+        // first four values are (1, 0, 0, 0); a column group beyond m reads
+        // zeros there too.  Choosing the address instead of the loaded value
+        // keeps the loads' destinations in A (no second set of registers).
 #pragma unroll
         for (int p = 0; p < PN; ++p) {
-            const int i = a + R * p;
-            const int e = (valid && i < n) ? rs + i : 0;
-            col[p] = g.scol[e];
-            cval[p] = g.scw[e];
+            col[p] = pe[p].x;
+            cval[p] = __int_as_float(pe[p].y);
         }
         const auto zp = gmem(g.zpad);
 #pragma unroll
@@ -726,8 +718,21 @@ __global__ __launch_bounds__(256, (W > 1) ? 1 : (P >= 16) ? 2 : (P <= 4) ? 5 : 3
     const QueryDev* qp = g.qd + qidx;
     const int m = valid ? qp->m : 0;
     const int ldk = qp->ldk;
+    // d is a document of the launch even for a team without one, so these
+    // loads need no guard (a guarded load would be waited for inside its branch)
     const int rs = g.sptr[d];
-    const int n = valid ? g.sptr[d + 1] - rs : 0;
+    const int re = g.sptr[d + 1];
+    // the one-wave teams' row entries (index, weight) of rows a + R p, read
+    // from the padded copy, whose address needs the document's rank only: they
+    // are in flight together with the row pointers, before the wait for n
+    static_assert(R * P <= kPadDocWidth, "a tile's rows fit the padded entries");
+    int2 pe[(W == 1) ? P : 1];
+    if constexpr (W == 1) {
+        const auto pp = gmem(g.pent) + (int64_t)(d - g.pad_d0) * kPadDocWidth + a;
+#pragma unroll
+        for (int p = 0; p < P; ++p) pe[p] = ld2i(pp + R * p);
+    }
+    const int n = valid ? re - rs : 0;
     const int kb = (wi * C + b) * Q;
 
     int it_end = valid ? min(g.it_begin + g.it_count, qp->iters) : g.it_begin;
@@ -744,12 +749,18 @@ __global__ __launch_bounds__(256, (W > 1) ? 1 : (P >= 16) ? 2 : (P <= 4) ? 5 : 3
     }
     const int my_end = valid ? min(g.it_begin + g.it_count, qp->iters) : g.it_begin;
 
-    // rows per lane for this wave (documents of a launch are sorted by length,
-    // so the teams of a wave have similar n); uniform, SGPR
-    const int pr = __builtin_amdgcn_readfirstlane(wave_max((n + R - 1) / R));
+    // rows per lane for this wave: the most any of its teams needs (documents
+    // of a launch are sorted by length, so the teams of a wave have similar n).
+    // n is uniform over a team, so its first lane stands for it; uniform, SGPR
+    const int nrl = (n + R - 1) / R;
+    int pr = __builtin_amdgcn_readlane(nrl, 0);
+    if constexpr (W == 1) {
+#pragma unroll
+        for (int t = 1; t < TPW; ++t) pr = max(pr, __builtin_amdgcn_readlane(nrl, t * T));
+    }
     sink_dispatch<R, C, P, Q, W, (P >= 16) ? 2 : 1, (P >= 16) ? 2 : 1>(
         pr, g, qp, valid, d, rs, n, m, ldk, a, b, tl, wi, team, kb, it_end, my_end, s_part, s_red, s_rho,
-        s_x + (XL ? (team * W + wi) * XTEAM : 0));
+        s_x + (XL ? (team * W + wi) * XTEAM : 0), pe);
 }
 
 // Any size: one 256-thread block per (query, document); the K block is
@@ -1101,15 +1112,13 @@ hipError_t launch_sinkhorn(int shape, const SinkArgs& a, int max_m, int max_n, h
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
         }
-        hipLaunchKernelGGL(k_sink_stream, dim3((unsigned)nitems), dim3(256), lds, s, a);
-        return hipGetLastError();
+        return launch_kernel(k_sink_stream, dim3((unsigned)nitems), dim3(256), (uint32_t)lds, s, a);
     }
     const Shape& sh = kShapes[shape];
     // register tiles: each query's documents padded to whole blocks; the row
     // kernel has one team per block, so this is nitems for it
     const int64_t blocks = (int64_t)a.nq * ((a.d_end - a.d_begin + sh.teams_per_block - 1) / sh.teams_per_block);
-    hipLaunchKernelGGL(sh.kern, dim3((unsigned)blocks), dim3(sh.threads), 0, s, a);
-    return hipGetLastError();
+    return launch_kernel(sh.kern, dim3((unsigned)blocks), dim3(sh.threads), 0, s, a);
 }
 
 }  // namespace wmd

@@ -14,7 +14,7 @@ namespace wmd {
 
 constexpr int kMaxQueryWords = 4096;   // streaming kernel LDS: 3 floats per query word
 constexpr int kMaxDocWords = 16384;    // streaming kernel LDS: 1 float per document word
-constexpr int kTileMaxDoc = 64;        // documents up to this length use the register tiles
+constexpr int kTileMaxDoc = kPadDocWidth;   // documents up to this length use the register tiles
 constexpr float kKmFromKMinLambda = 0.5f;  // from this lambda on, K .* M is rebuilt from K
 
 // Device buffers of one query call.  A corpus has kWorkSlots of them, used
@@ -102,10 +102,12 @@ struct wmd_corpus {
     int64_t device_bytes = 0;
     std::mutex mu;
     hipStream_t stream = nullptr;       // stream of the synchronous entry points
-    // timing ring: slot i holds the events of one timed call (start, after
-    // the distance kernel, end); a slot is folded into the totals before reuse
+    // timing ring: slot i holds the events of one timed call (distance phase
+    // start and end, Sinkhorn phase start and end, each taken from the phase's
+    // own kernel dispatches); a slot is folded into the totals before reuse
     static constexpr int kTimingSlots = 64;
-    hipEvent_t ev[kTimingSlots][3] = {};
+    static constexpr int kTimingEvents = 4;
+    hipEvent_t ev[kTimingSlots][kTimingEvents] = {};
     bool slot_pending[kTimingSlots] = {};
     int next_slot = 0, last_slot = -1;
     int32_t timing = 0;                 // 0: off; k: record every k-th call
