@@ -315,6 +315,20 @@ int wmd_timing_get(wmd_corpus* corpus, wmd_timing* out);
  * any batch is on the device.  Every query's result is bitwise the one
  * wmd_query returns for it with the same options: a document's computation
  * does not depend on the rest of the batch.
+ *
+ * Step mode (step_iters > 0): iteration-level continuous batching on one
+ * stream.  Each admitted query holds its own region of the budget (K block,
+ * iterate x, results: about 4 (U + N) ldk bytes) until it completes, and at
+ * most max_batch queries are in flight.  The worker enqueues steps (at most
+ * two ahead): a step runs the distance kernel of the queries admitted into
+ * it, then one Sinkhorn launch per shape class over every in-flight query,
+ * each advancing step_iters iterations from its own count (with the final
+ * step once it reaches its iteration count), then downloads the results of
+ * the queries that finished.  Queries join and leave between steps, so a
+ * short query does not wait for a long one to finish.  Results are bitwise
+ * those of wmd_query (the iterate is kept in FP32 between launches, as in a
+ * call with iters_per_launch).  Needs tol = 0, lse = 0, iters_per_launch = 0;
+ * batch_wait_us and max_inflight are not used.
  */
 typedef struct wmd_server wmd_server;
 
@@ -329,7 +343,11 @@ typedef struct wmd_server_options {
     wmd_query_options query;   /* options of every query */
     int32_t max_batch_words;   /* cap on the query words of one batch (its work), so a
                                   burst of queries does not form one long batch; a
-                                  query longer than the cap runs alone (0: no cap) */
+                                  query longer than the cap runs alone (0: no cap).
+                                  Step mode: cap on the words in flight */
+    int32_t step_iters;        /* 0: batch mode.  > 0: step mode (iteration-level
+                                  batching, below), each step advancing every
+                                  in-flight query by this many iterations */
 } wmd_server_options;
 
 typedef struct wmd_server_stats {
@@ -345,13 +363,14 @@ typedef struct wmd_server_stats {
 } wmd_server_stats;
 
 /* Defaults: 4 GiB budget, batches of 16 and at most 512 query words, 2
- * streams, no residuals, no batching wait, default query options. */
+ * streams, no residuals, no batching wait, default query options, batch
+ * mode. */
 void wmd_server_options_init(wmd_server_options* opt);
 
 /* Create a server on `corpus` (which must outlive it).  Errors: WMD_EINVAL for
  * bad options (budget < 256, max_batch < 1, max_inflight outside 1..16,
- * invalid query options, BF16 without BF16 corpus copies), WMD_ENOMEM,
- * WMD_EDEVICE. */
+ * step_iters < 0, invalid query options, BF16 without BF16 corpus copies,
+ * step mode with lse, tol or iters_per_launch), WMD_ENOMEM, WMD_EDEVICE. */
 int wmd_server_create(wmd_corpus* corpus, const wmd_server_options* opt, wmd_server** out);
 
 /* Queue one query (arguments as wmd_query; host arrays copied before return).

@@ -467,6 +467,7 @@ int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wm
         d.inv_lambda = d.km_from_k ? 1.0f / q.lambda : 0.f;
         d.tol = opt.tol;
         d.it_out = dev_iters ? dev_iters + (size_t)b * N : nullptr;
+        d.it_base = 0;
         std::memcpy(hid + mo, q.ids.data(), sizeof(int32_t) * q.m);
         std::memcpy(hr + mo, q.r.data(), sizeof(float) * q.m);
         std::memcpy(hri + mo, q.rinv.data(), sizeof(float) * q.m);
@@ -524,7 +525,7 @@ int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wm
     const int32_t* dqg = reinterpret_cast<const int32_t*>(dp + off_qg);
     if (opt.lse) e = launch_dist_lse(dc, dq, dqg, B, (int)sum_ldk, stream);
     else if (narrow) e = launch_dist_narrow(dc, hq[0], dq, hp, pbytes, off_id, dp, bf16, stream);
-    else e = launch_dist(dc, dq, dqg, B, (int)sum_ldk, bf16, opt.log_domain, w.nrow, stream);
+    else e = launch_dist(dc, dq, dqg, B, (int)sum_ldk, bf16, opt.log_domain, stream);
     if (e != hipSuccess) return hip_fail(e, "query: distance kernel launch");
     ++launches;
     if (slot >= 0) {

@@ -543,19 +543,25 @@ __global__ __launch_bounds__(256) void k_fill_inf(float* p, int64_t n) {
         p[e] = INFINITY;
 }
 
+// The row-minimum arrays of B queries (wherever each lies) set to +inf, query
+// b in grid row b.
+__global__ __launch_bounds__(256) void k_fill_nrow_inf(const QueryDev* qd, int64_t U) {
+    float* p = qd[blockIdx.y].nrow;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < U; e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = INFINITY;
+}
+
 }  // namespace
 
 hipError_t launch_dist(const DevCorpus& c, const QueryDev* qd, const int32_t* kofs, int B, int ncols, int bf16,
-                       int shift, float* nrow_all, hipStream_t s) {
+                       int shift, hipStream_t s) {
     if (B <= 0 || c.U <= 0 || ncols <= 0) return hipSuccess;
     if (c.ldv % 64 != 0) return hipErrorInvalidValue;   // whole chunks
     hipError_t e;
-    if (shift) {
-        const int64_t n = c.U * (int64_t)B;
-        if ((e = launch_kernel(k_fill_inf, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0, s,
-                               nrow_all, n)) != hipSuccess)
-            return e;
-    }
+    if (shift && (e = launch_kernel(k_fill_nrow_inf, dim3((unsigned)std::min<int64_t>((c.U + 255) / 256, 1024),
+                                                          (unsigned)B),
+                                    dim3(256), 0, s, qd, c.U)) != hipSuccess)
+        return e;
     DistArgs a;
     a.act = c.act;
     a.act16 = c.act_bf16;

@@ -274,6 +274,18 @@ __device__ __forceinline__ double team_sum_f64(double v) {
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// A launch whose queries each carry their own progress (per_query: the
+// step-wise server, where queries join and leave between launches) runs each
+// query's it_count iterations from its it_base, with the final step once the
+// query's iterations are done; other launches share one range.  Uniform over
+// a block (the query is), so the fields stay scalar.
+__device__ __forceinline__ void take_iteration_range(SinkArgs& g, const QueryDev* qp) {
+    if (g.per_query) {
+        g.it_begin = qp->it_base;
+        g.final_step = (int64_t)qp->it_base + g.it_count >= qp->iters ? 1 : 0;
+    }
+}
+
 // added to every x update (see sink_team)
 constexpr float kXPad = 0x1p-126f;
 
@@ -716,6 +728,7 @@ __global__ __launch_bounds__(256, (W > 1) ? 1 : (P >= 16) ? 2 : (P <= 4) ? 5 : 3
     const int qidx = g.single ? 0 : g.qlist[qi < g.nq ? qi : 0];
     const int d = g.d_begin + (valid ? dd : 0);
     const QueryDev* qp = g.qd + qidx;
+    take_iteration_range(g, qp);
     const int m = valid ? qp->m : 0;
     const int ldk = qp->ldk;
     // d is a document of the launch even for a team without one, so these
@@ -775,6 +788,7 @@ __global__ __launch_bounds__(256) void k_sink_stream(SinkArgs g) {
     const int qidx = g.single ? 0 : g.qlist[item / nd];
     const int d = g.d_begin + (int)(item % nd);
     const QueryDev* qp = g.qd + qidx;
+    take_iteration_range(g, qp);
     const int m = qp->m, ldk = qp->ldk;
     const int rs = g.sptr[d], n = g.sptr[d + 1] - rs;
     float* x = sh;
@@ -900,6 +914,7 @@ __global__ __launch_bounds__(64) void k_sink_rows(SinkArgs g) {
     const int qidx = g.single ? 0 : g.qlist[item / nd];
     const int d = g.d_begin + (int)(item % nd);
     const QueryDev* qp = g.qd + qidx;
+    take_iteration_range(g, qp);
     const int m = qp->m, ldk = qp->ldk;
     const int rs = g.sptr[d];
     const int n = g.sptr[d + 1] - rs;

@@ -2,6 +2,18 @@
 // batches as streams and device memory free up, so batches overlap on the
 // device; results and latency statistics are kept per ticket.
 //
+// Two schedules.  Batch mode: each admitted batch runs its whole path (K1,
+// every iteration, final step, download) on a stream of its own.  Step mode
+// (step_iters > 0, iteration-level batching): every in-flight query holds its
+// own device region (K block, iterate x, results) across launches, and the
+// worker enqueues steps on one stream; a step runs K1 for the queries admitted
+// into it, then one Sinkhorn launch per shape class over all in-flight
+// queries, each advancing step_iters iterations from its own iteration count
+// (the final step included once its count is reached), then downloads the
+// results of the queries that finished.  Queries join and leave at step
+// boundaries, so a short query admitted next to a long one finishes after
+// its own few steps.
+//
 // Memory: one device allocation of the whole HBM budget, carved per batch by
 // a first-fit pool (byte accounting: a batch is admitted when its workspace
 // fits the largest free range, and its bytes return to the pool when it
@@ -49,6 +61,45 @@ struct Slot {
     int status = WMD_OK;
 };
 
+// Step mode: one in-flight query, its device region in the pool (K block,
+// K .* M when lambda is small, row shifts with the column shift, iterate x,
+// results) and its progress.
+struct Active {
+    int64_t id = 0;
+    const PlannedQuery* q = nullptr;   // the ticket's (tickets do not move)
+    size_t off = 0, bytes = 0;         // pool range
+    int hslot = -1;                    // pinned result buffer
+    int it_base = 0;                   // x updates done before the next step
+    int shape = -1;                    // Sinkhorn launch shape
+    bool fresh = true;                 // its distance kernel has not run yet
+    float* Kt = nullptr;
+    float* KMt = nullptr;
+    float* nrow = nullptr;
+    float* x = nullptr;
+    double* out = nullptr;             // N distances, then N residuals
+};
+
+struct Step {
+    hipEvent_t ev = nullptr;
+    std::vector<Active> finishing;     // queries whose results this step downloads
+    int queries = 0;                   // queries the step advanced
+};
+
+struct StepState {
+    static constexpr int kRing = 2;    // steps in flight at most
+    hipStream_t stream = nullptr;
+    std::vector<Active> active;        // in-flight queries (worker thread only)
+    Step ring[kRing];
+    int next = 0;                      // ring entry of the next step
+    std::deque<int> order;             // ring entries in flight, oldest first
+    char* dparams[kRing] = {};         // device parameter block of each ring entry
+    size_t dcap[kRing] = {};
+    char* hparams[kRing] = {};         // its pinned host image
+    size_t hcap[kRing] = {};
+    double* h_out = nullptr;           // max_batch pinned result buffers
+    std::vector<int> free_hslots;
+};
+
 }  // namespace
 
 struct wmd_server {
@@ -67,6 +118,7 @@ struct wmd_server {
     RegionPool pool;
     std::vector<Slot*> slots;
     std::thread worker;
+    StepState* steps = nullptr;        // step mode only
     // statistics
     int64_t submitted = 0, completed = 0, batches = 0, batched_queries = 0;
     double doc_iters = 0.0;
@@ -222,6 +274,354 @@ void worker_main(wmd_server* S) {
     }
 }
 
+// ---- step mode ----
+
+size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+size_t al64(size_t b) { return (b + 63) & ~(size_t)63; }
+
+// Device bytes of one query's region in step mode.
+size_t region_bytes(const wmd_corpus* c, const PlannedQuery& q, const wmd_query_options& o, bool resid) {
+    const size_t U = (size_t)c->dc.U, N = (size_t)c->dc.N, ldk = (size_t)q.ldk;
+    size_t b = al256(sizeof(float) * U * ldk);                                       // K block
+    if (q.lambda < kKmFromKMinLambda) b += al256(sizeof(float) * U * ldk);           // K .* M
+    if (o.log_domain) b += al256(sizeof(float) * U);                                 // row shifts
+    b += al256(sizeof(float) * N * ldk);                                             // x
+    b += al256(sizeof(double) * N * (resid ? 2 : 1));                                // results
+    return b;
+}
+
+void carve_region(const wmd_server* S, Active& a) {
+    const wmd_corpus* c = S->corpus;
+    const size_t U = (size_t)c->dc.U, N = (size_t)c->dc.N, ldk = (size_t)a.q->ldk;
+    char* p = S->base + a.off;
+    auto take = [&](size_t bytes) {
+        char* r = p;
+        p += al256(bytes);
+        return r;
+    };
+    a.Kt = reinterpret_cast<float*>(take(sizeof(float) * U * ldk));
+    a.KMt = a.q->lambda < kKmFromKMinLambda ? reinterpret_cast<float*>(take(sizeof(float) * U * ldk)) : nullptr;
+    a.nrow = S->opt.query.log_domain ? reinterpret_cast<float*>(take(sizeof(float) * U)) : nullptr;
+    a.x = reinterpret_cast<float*>(take(sizeof(float) * N * ldk));
+    a.out = reinterpret_cast<double*>(take(sizeof(double) * N * (S->opt.want_resid ? 2 : 1)));
+}
+
+// Grow a step's parameter buffers (its previous step has retired, so neither
+// is in use).
+int ensure_step_buffers(StepState& st, int k, size_t bytes) {
+    hipError_t e;
+    if (bytes > st.dcap[k]) {
+        if (st.dparams[k]) (void)hipFree(st.dparams[k]);
+        st.dparams[k] = nullptr;
+        st.dcap[k] = 0;
+        const size_t cap = bytes + bytes / 2;
+        if ((e = device_alloc(reinterpret_cast<void**>(&st.dparams[k]), cap)) != hipSuccess)
+            return hip_fail(e, "server: step parameters");
+        st.dcap[k] = cap;
+    }
+    if (bytes > st.hcap[k]) {
+        if (st.hparams[k]) (void)hipHostFree(st.hparams[k]);
+        st.hparams[k] = nullptr;
+        st.hcap[k] = 0;
+        const size_t cap = bytes + bytes / 2;
+        if ((e = hipHostMalloc(reinterpret_cast<void**>(&st.hparams[k]), cap, hipHostMallocDefault)) != hipSuccess)
+            return hip_fail(e, "server: pinned step parameters");
+        st.hcap[k] = cap;
+    }
+    return WMD_OK;
+}
+
+// Move queued queries into the in-flight set, FIFO without overtaking, while
+// a result buffer is free, the query's region fits the largest free range of
+// the budget and the in-flight words stay within max_batch_words (lock held).
+void admit_step(wmd_server* S) {
+    StepState& st = *S->steps;
+    const bool resid = S->opt.want_resid != 0;
+    int64_t words = 0;
+    for (const Active& a : st.active) words += a.q->m;
+    while (!S->pending.empty() && !st.free_hslots.empty()) {
+        const Ticket& t = S->tickets.at(S->pending.front());
+        if (!st.active.empty() && S->opt.max_batch_words > 0 && words + t.q.m > S->opt.max_batch_words) break;
+        Active a;
+        a.id = S->pending.front();
+        a.q = &t.q;
+        a.bytes = region_bytes(S->corpus, t.q, S->opt.query, resid);
+        if (!S->pool.alloc(a.bytes, &a.off)) break;
+        a.hslot = st.free_hslots.back();
+        st.free_hslots.pop_back();
+        a.shape = sinkhorn_shape_for(t.q.m, kTileMaxDoc, false);
+        carve_region(S, a);
+        words += t.q.m;
+        S->pending.pop_front();
+        // fresh queries go first: the step's distance kernel covers the first records
+        size_t pos = 0;
+        while (pos < st.active.size() && st.active[pos].fresh) ++pos;
+        st.active.insert(st.active.begin() + (std::ptrdiff_t)pos, a);
+    }
+}
+
+// Enqueue one step over the in-flight queries on ring entry k (worker thread,
+// without the lock).  `finishing` receives the queries this step completes.
+int enqueue_step(wmd_server* S, int k, std::vector<Active>& act, std::vector<Active>& finishing) {
+    StepState& st = *S->steps;
+    wmd_corpus* c = S->corpus;
+    const DevCorpus& dc = c->dc;
+    const wmd_query_options& o = S->opt.query;
+    const int A = (int)act.size();
+    const int64_t N = dc.N;
+    const int iters_step = S->opt.step_iters;
+    int nnew = 0;
+    size_t m_new = 0, m_all = 0;
+    for (const Active& a : act) {
+        if (a.fresh) {
+            ++nnew;
+            m_new += (size_t)a.q->m;
+        }
+        m_all += (size_t)a.q->m;
+    }
+    // parameter block: QueryDev[A] | qlist[A] | kofs[nnew + 1] | qid of the new
+    // queries | r | 1/r of every query
+    const size_t off_ql = al64(sizeof(QueryDev) * A);
+    const size_t off_qg = al64(off_ql + sizeof(int32_t) * A);
+    const size_t off_id = al64(off_qg + sizeof(int32_t) * (nnew + 1));
+    const size_t off_r = al64(off_id + sizeof(int32_t) * m_new);
+    const size_t off_ri = al64(off_r + sizeof(float) * m_all);
+    const size_t pbytes = al64(off_ri + sizeof(float) * m_all);
+    int rc = ensure_step_buffers(st, k, pbytes);
+    if (rc) return rc;
+    char* hp = st.hparams[k];
+    char* dp = st.dparams[k];
+    std::memset(hp, 0, pbytes);
+    QueryDev* hq = reinterpret_cast<QueryDev*>(hp);
+    int32_t* hql = reinterpret_cast<int32_t*>(hp + off_ql);
+    int32_t* hqg = reinterpret_cast<int32_t*>(hp + off_qg);
+    const float tau = o.recompute_below >= 0.f ? o.recompute_below : (o.precision == WMD_DIST_BF16 ? 1e-2f : 0.5f);
+    size_t mi = 0, mr = 0;
+    hqg[0] = 0;
+    for (int b = 0; b < A; ++b) {
+        const Active& a = act[b];
+        const PlannedQuery& q = *a.q;
+        QueryDev& d = hq[b];
+        if (a.fresh) {
+            d.qid = reinterpret_cast<const int32_t*>(dp + off_id) + mi;
+            std::memcpy(hp + off_id + sizeof(int32_t) * mi, q.ids.data(), sizeof(int32_t) * q.m);
+            mi += (size_t)q.m;
+            hqg[b + 1] = hqg[b] + q.ldk;
+        }
+        d.r = reinterpret_cast<const float*>(dp + off_r) + mr;
+        d.rinv = reinterpret_cast<const float*>(dp + off_ri) + mr;
+        std::memcpy(hp + off_r + sizeof(float) * mr, q.r.data(), sizeof(float) * q.m);
+        std::memcpy(hp + off_ri + sizeof(float) * mr, q.rinv.data(), sizeof(float) * q.m);
+        mr += (size_t)q.m;
+        d.Kt = a.Kt;
+        d.KMt = a.KMt;
+        d.nrow = a.nrow;
+        d.x = a.x;
+        d.out = a.out;
+        d.resid = S->opt.want_resid ? a.out + N : nullptr;
+        d.lambda = q.lambda;
+        d.tau2 = tau * tau;
+        d.m = q.m;
+        d.ldk = q.ldk;
+        d.iters = q.iters;
+        d.shift = o.log_domain ? 1 : 0;
+        d.km_from_k = q.lambda >= kKmFromKMinLambda ? 1 : 0;
+        d.inv_lambda = d.km_from_k ? 1.0f / q.lambda : 0.f;
+        d.tol = 0.f;
+        d.it_out = nullptr;
+        d.it_base = a.it_base;
+    }
+    // Sinkhorn launches grouped by shape, the streaming-only queries first
+    const int nshape = sinkhorn_num_shapes();
+    std::vector<int> start(nshape + 2, 0);
+    for (const Active& a : act) start[a.shape + 2]++;
+    for (int sh = 0; sh <= nshape; ++sh) start[sh + 1] += start[sh];
+    {
+        std::vector<int> fill(start.begin(), start.end() - 1);
+        for (int b = 0; b < A; ++b) hql[fill[act[b].shape + 1]++] = b;
+    }
+
+    const hipStream_t s = st.stream;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(dp, hp, pbytes, hipMemcpyHostToDevice, s)) != hipSuccess)
+        return hip_fail(e, "server: step parameters");
+    const QueryDev* dq = reinterpret_cast<const QueryDev*>(dp);
+    const int32_t* dql = reinterpret_cast<const int32_t*>(dp + off_ql);
+    if (nnew > 0 &&
+        (e = launch_dist(dc, dq, reinterpret_cast<const int32_t*>(dp + off_qg), nnew, hqg[nnew],
+                         o.precision == WMD_DIST_BF16 ? 1 : 0, o.log_domain, s)) != hipSuccess)
+        return hip_fail(e, "server: distance kernel launch");
+    const int d_tile = (int)c->d_tile;
+    auto go = [&](int shape, int q0, int q1, int d0, int d1) -> hipError_t {
+        if (q1 <= q0 || d1 <= d0) return hipSuccess;
+        SinkArgs g;
+        g.sptr = dc.sptr;
+        g.scol = dc.scol;
+        g.scw = dc.scw;
+        g.sdoc = dc.sdoc;
+        g.zpad = dc.zpad;
+        g.pent = dc.pent;
+        g.pad_d0 = (int32_t)dc.pad_d0;
+        g.it_begin = 0;
+        g.it_count = iters_step;
+        g.final_step = 0;
+        g.per_query = 1;
+        g.qlist = dql + q0;
+        g.nq = q1 - q0;
+        g.single = (g.nq == 1) ? 1 : 0;
+        g.qd = g.single ? dq + hql[q0] : dq;
+        g.d_begin = d0;
+        g.d_end = d1;
+        int mm = 0;
+        for (int i = q0; i < q1; ++i) mm = std::max(mm, act[hql[i]].q->m);
+        return launch_sinkhorn(shape, g, mm, c->h_sorted_len[d0], s);
+    };
+    if ((e = go(-1, start[0], start[1], 0, (int)N)) != hipSuccess ||
+        (e = go(-1, start[1], A, 0, d_tile)) != hipSuccess)
+        return hip_fail(e, "server: sinkhorn launch");
+    for (int sh = 0; sh < nshape; ++sh)
+        if ((e = go(sh, start[sh + 1], start[sh + 2], d_tile, (int)N)) != hipSuccess)
+            return hip_fail(e, "server: sinkhorn launch");
+    // results of the queries that reach their iteration count in this step
+    const size_t per = sizeof(double) * (size_t)N * (S->opt.want_resid ? 2 : 1);
+    for (const Active& a : act) {
+        if ((int64_t)a.it_base + iters_step < a.q->iters) continue;
+        if ((e = hipMemcpyAsync(reinterpret_cast<char*>(st.h_out) + per * (size_t)a.hslot, a.out, per,
+                                hipMemcpyDeviceToHost, s)) != hipSuccess)
+            return hip_fail(e, "server: download results");
+        finishing.push_back(a);
+    }
+    if ((e = hipEventRecord(st.ring[k].ev, s)) != hipSuccess) return hip_fail(e, "server: record");
+    return WMD_OK;
+}
+
+// Hand the results of a finished step's queries to their tickets and return
+// their memory (lock held on entry and exit).
+void retire_step(wmd_server* S, Step& sp, int status, std::unique_lock<std::mutex>& lk) {
+    StepState& st = *S->steps;
+    const int64_t N = S->corpus->dc.N;
+    const bool resid = S->opt.want_resid != 0;
+    const size_t per = (size_t)N * (resid ? 2 : 1);
+    std::vector<Ticket*> ts;
+    for (const Active& a : sp.finishing) ts.push_back(&S->tickets.at(a.id));
+    lk.unlock();
+    if (status == WMD_OK) {
+        for (size_t i = 0; i < ts.size(); ++i) {
+            const double* h = st.h_out + per * (size_t)sp.finishing[i].hslot;
+            ts[i]->dist.assign(h, h + N);
+            if (resid) ts[i]->resid.assign(h + N, h + 2 * N);
+        }
+    }
+    lk.lock();
+    const Clock::time_point now = Clock::now();
+    for (size_t i = 0; i < ts.size(); ++i) {
+        Ticket* t = ts[i];
+        t->status = status;
+        t->t_done = now;
+        t->done.store(true, std::memory_order_release);
+        if (status == WMD_OK) {
+            S->completed += 1;
+            S->doc_iters += (double)N * t->q.iters;
+            S->latencies_ms.push_back(std::chrono::duration<double, std::milli>(now - t->t_submit).count());
+        }
+        S->pool.release(sp.finishing[i].off, sp.finishing[i].bytes);
+        st.free_hslots.push_back(sp.finishing[i].hslot);
+    }
+    if (!ts.empty()) S->t_last = now;
+    sp.finishing.clear();
+    S->cv_done.notify_all();
+}
+
+void step_worker_main(wmd_server* S) {
+    (void)hipSetDevice(S->corpus->dc.device);
+    StepState& st = *S->steps;
+    std::unique_lock<std::mutex> lk(S->mu);
+    for (;;) {
+        // retire finished steps, oldest first
+        while (!st.order.empty()) {
+            Step& sp = st.ring[st.order.front()];
+            const hipError_t e = hipEventQuery(sp.ev);
+            if (e == hipErrorNotReady) break;
+            retire_step(S, sp, e == hipSuccess ? WMD_OK : WMD_EDEVICE, lk);
+            st.order.pop_front();
+        }
+        if (S->stop && S->pending.empty() && st.active.empty() && st.order.empty()) break;
+        if ((int)st.order.size() < StepState::kRing) {
+            admit_step(S);
+            if (!st.active.empty()) {
+                const int k = st.next;
+                st.next = (st.next + 1) % StepState::kRing;
+                std::vector<Active> act = st.active;   // the worker alone changes st.active
+                S->batches += 1;
+                S->batched_queries += (int64_t)act.size();
+                lk.unlock();
+                std::vector<Active> finishing;
+                const int rc = enqueue_step(S, k, act, finishing);
+                if (rc != WMD_OK) (void)hipStreamSynchronize(st.stream);   // drain what was enqueued
+                lk.lock();
+                Step& sp = st.ring[k];
+                if (rc != WMD_OK) {
+                    // the step failed: every query it carried fails with it
+                    sp.finishing = st.active;
+                    st.active.clear();
+                    retire_step(S, sp, rc, lk);
+                    continue;
+                }
+                sp.finishing = std::move(finishing);
+                sp.queries = (int)act.size();
+                st.order.push_back(k);
+                // advance the in-flight set: finishing queries leave it (their
+                // memory returns when the step retires)
+                std::vector<Active> keep;
+                for (Active a : st.active) {
+                    a.fresh = false;
+                    a.it_base += S->opt.step_iters;
+                    if (a.it_base < a.q->iters) keep.push_back(a);
+                }
+                st.active.swap(keep);
+                continue;
+            }
+        }
+        if (!st.order.empty()) {
+            lk.unlock();
+            std::this_thread::yield();
+            lk.lock();
+        } else {
+            S->cv_work.wait(lk, [&] { return S->stop || !S->pending.empty(); });
+        }
+    }
+}
+
+void step_state_free(StepState* st) {
+    if (!st) return;
+    if (st->stream) (void)hipStreamSynchronize(st->stream);
+    for (int k = 0; k < StepState::kRing; ++k) {
+        if (st->ring[k].ev) (void)hipEventDestroy(st->ring[k].ev);
+        if (st->dparams[k]) (void)hipFree(st->dparams[k]);
+        if (st->hparams[k]) (void)hipHostFree(st->hparams[k]);
+    }
+    if (st->h_out) (void)hipHostFree(st->h_out);
+    if (st->stream) (void)hipStreamDestroy(st->stream);
+    delete st;
+}
+
+int step_state_create(wmd_server* S) {
+    StepState* st = new StepState();
+    S->steps = st;
+    hipError_t e;
+    if ((e = hipStreamCreateWithFlags(&st->stream, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(e, "server: step stream");
+    for (int k = 0; k < StepState::kRing; ++k)
+        if ((e = hipEventCreateWithFlags(&st->ring[k].ev, hipEventDisableTiming)) != hipSuccess)
+            return hip_fail(e, "server: step events");
+    const size_t per = sizeof(double) * (size_t)S->corpus->dc.N * (S->opt.want_resid ? 2 : 1);
+    if ((e = hipHostMalloc(reinterpret_cast<void**>(&st->h_out), per * (size_t)S->opt.max_batch,
+                           hipHostMallocDefault)) != hipSuccess)
+        return hip_fail(e, "server: pinned results");
+    for (int i = S->opt.max_batch - 1; i >= 0; --i) st->free_hslots.push_back(i);
+    return WMD_OK;
+}
+
 void server_free(wmd_server* S) {
     for (Slot* sl : S->slots) {
         if (sl->stream) (void)hipStreamSynchronize(sl->stream);
@@ -231,6 +631,8 @@ void server_free(wmd_server* S) {
         delete sl;
     }
     S->slots.clear();
+    step_state_free(S->steps);
+    S->steps = nullptr;
     if (S->base) (void)hipFree(S->base);
     delete S;
 }
@@ -266,6 +668,7 @@ void wmd_server_options_init(wmd_server_options* opt) {
     opt->batch_wait_us = 0;
     wmd_query_options_init(&opt->query);
     opt->max_batch_words = 512;
+    opt->step_iters = 0;
 }
 
 int wmd_server_create(wmd_corpus* corpus, const wmd_server_options* opt_in, wmd_server** out) {
@@ -279,10 +682,13 @@ int wmd_server_create(wmd_corpus* corpus, const wmd_server_options* opt_in, wmd_
     if (opt.max_inflight < 1 || opt.max_inflight > 16) return fail(WMD_EINVAL, "server: max_inflight outside 1..16");
     if (opt.batch_wait_us < 0) return fail(WMD_EINVAL, "server: batch_wait_us < 0");
     if (opt.max_batch_words < 0) return fail(WMD_EINVAL, "server: max_batch_words < 0");
+    if (opt.step_iters < 0) return fail(WMD_EINVAL, "server: step_iters < 0");
     wmd_query_options qo;
     int rc = check_query_options(&opt.query, &qo);
     if (rc) return rc;
     if (qo.tile != -1) return fail(WMD_EINVAL, "server: the query tile must be automatic (-1)");
+    if (opt.step_iters > 0 && (qo.lse || qo.tol > 0.f || qo.iters_per_launch > 0))
+        return fail(WMD_EINVAL, "server: step mode runs the plain iteration (no lse, tol or iters_per_launch)");
     if (qo.precision == WMD_DIST_BF16 && !corpus->dc.act_bf16)
         return fail(WMD_EINVAL, "server: BF16 distances need a corpus created with bf16 copies");
     opt.query = qo;
@@ -299,6 +705,15 @@ int wmd_server_create(wmd_corpus* corpus, const wmd_server_options* opt_in, wmd_
         S->base = nullptr;
         server_free(S);
         return code;
+    }
+    if (opt.step_iters > 0) {
+        if ((rc = step_state_create(S)) != WMD_OK) {
+            server_free(S);
+            return rc;
+        }
+        S->worker = std::thread(step_worker_main, S);
+        *out = S;
+        return WMD_OK;
     }
     for (int i = 0; i < opt.max_inflight; ++i) {
         Slot* sl = new Slot();
@@ -332,7 +747,9 @@ int64_t wmd_server_submit(wmd_server* S, const int32_t* qids, const float* qweig
     int rc = plan_query(S->corpus, qids, qweights, n, lambda, iters, S->opt.query.precision == WMD_DIST_BF16, &q);
     if (rc) return rc;
     const std::vector<PlannedQuery> one{q};
-    const size_t need = make_layout(S->corpus, one, S->opt.query, S->opt.want_resid != 0, true).device_bytes();
+    const size_t need = S->opt.step_iters > 0
+                            ? region_bytes(S->corpus, q, S->opt.query, S->opt.want_resid != 0)
+                            : make_layout(S->corpus, one, S->opt.query, S->opt.want_resid != 0, true).device_bytes();
     if (RegionPool::rounded(need) > S->pool.capacity())
         return fail(WMD_ENOMEM, "server: query needs %zu device bytes, the whole budget is %zu", need,
                     S->pool.capacity());
@@ -428,6 +845,10 @@ int wmd_server_stats_reset(wmd_server* S) {
     std::lock_guard<std::mutex> lk(S->mu);
     S->submitted = (int64_t)S->pending.size();
     for (Slot* sl : S->slots) S->submitted += (int64_t)sl->ids.size();
+    if (S->steps) {
+        S->submitted += (int64_t)S->steps->active.size();
+        for (int k : S->steps->order) S->submitted += (int64_t)S->steps->ring[k].finishing.size();
+    }
     S->completed = S->batches = S->batched_queries = 0;
     S->doc_iters = 0.0;
     S->latencies_ms.clear();

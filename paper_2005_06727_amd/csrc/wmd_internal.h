@@ -36,6 +36,7 @@ struct QueryDev {
     float inv_lambda;      // 1 / lambda (km_from_k only)
     float tol;             // > 0: stop a document once its x-change residual <= tol
     int32_t* it_out;       // N x updates made per document (input order) or nullptr
+    int32_t it_base;       // x updates done before this launch (per-query launches only)
 };
 
 // Device-resident corpus (all arrays on `device`).
@@ -89,6 +90,10 @@ struct SinkArgs {
     // (the register tiles read rows from them; their documents are >= pad_d0)
     const int2* pent = nullptr;
     int32_t pad_d0 = 0;
+    // nonzero: each query runs it_count iterations from its own it_base (its
+    // record), with the final step when that reaches its iteration count;
+    // it_begin and final_step are then ignored
+    int32_t per_query = 0;
 };
 
 // Kernel timing by dispatch.  While `stop` is set on the calling thread, the
@@ -131,10 +136,11 @@ hipError_t launch_gather_rows(const float* vecs, const int32_t* ids, float* out,
 // Distance GEMM + epilogue: writes Kt / KMt of every query; the queries are
 // split into `groups` contiguous groups, qgroup[g] .. qgroup[g+1] (device).
 // K1 over all queries of a call: kofs[B + 1] holds each query's first column
-// (prefix sums of ldk, kofs[B] = ncols).  With shift, nrow_all (U x B floats)
-// receives the row minima and a second pass turns Kt into exp(-lambda (d - n)).
+// (prefix sums of ldk, kofs[B] = ncols).  With shift, each query's nrow (U
+// floats) receives its row minima and a second pass turns Kt into
+// exp(-lambda (d - n)).
 hipError_t launch_dist(const DevCorpus& c, const QueryDev* qd, const int32_t* kofs, int B, int ncols, int bf16,
-                       int shift, float* nrow_all, hipStream_t s);
+                       int shift, hipStream_t s);
 // k smallest (distance, index) pairs of n distances, ascending; scratch of
 // topk_scratch_bytes(n, k) device bytes.  k <= kMaxTopK.
 constexpr int kMaxTopK = WMD_MAX_TOPK;

@@ -68,7 +68,7 @@ class wmd_timing(C.Structure):
 class wmd_server_options(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_batch", C.c_int32), ("max_inflight", C.c_int32),
                 ("want_resid", C.c_int32), ("batch_wait_us", C.c_int32), ("query", wmd_query_options),
-                ("max_batch_words", C.c_int32)]
+                ("max_batch_words", C.c_int32), ("step_iters", C.c_int32)]
 
 
 class wmd_server_stats(C.Structure):
@@ -403,7 +403,8 @@ def wmd_server_options_init() -> wmd_server_options:
 
 def wmd_server_create(corpus: int, hbm_budget_bytes: Optional[int] = None, max_batch: Optional[int] = None,
                       max_inflight: Optional[int] = None, want_resid: bool = False,
-                      batch_wait_us: int = 0, max_batch_words: Optional[int] = None, **opts) -> int:
+                      batch_wait_us: int = 0, max_batch_words: Optional[int] = None, step_iters: int = 0,
+                      **opts) -> int:
     o = wmd_server_options_init()
     if hbm_budget_bytes is not None:
         o.hbm_budget_bytes = int(hbm_budget_bytes)
@@ -415,6 +416,7 @@ def wmd_server_create(corpus: int, hbm_budget_bytes: Optional[int] = None, max_b
     o.batch_wait_us = int(batch_wait_us)
     if max_batch_words is not None:
         o.max_batch_words = int(max_batch_words)
+    o.step_iters = int(step_iters)
     o.query = _qopts(**opts)
     h = _P()
     _check(_lib.wmd_server_create(corpus, C.byref(o), C.byref(h)))

@@ -74,8 +74,8 @@ def test_product_path_does_not_import_oracle():
 
 def test_server_option_defaults_and_null_corpus():
     o = wmd.wmd_server_options_init()
-    assert (o.hbm_budget_bytes, o.max_batch, o.max_inflight, o.want_resid, o.batch_wait_us, o.max_batch_words) == (
-        4 << 30, 16, 2, 0, 0, 512)
+    assert (o.hbm_budget_bytes, o.max_batch, o.max_inflight, o.want_resid, o.batch_wait_us, o.max_batch_words,
+            o.step_iters) == (4 << 30, 16, 2, 0, 0, 512, 0)
     assert (o.query.precision, o.query.tile) == (0, -1)
     with pytest.raises(wmd.WmdError) as e:
         wmd.wmd_server_create(None)

@@ -209,3 +209,86 @@ def test_destroy_drains_pending(ragged, wmd):
     q, qw = qs[0]
     want, _ = sinkhorn_wmd_sparse(vecs, q, qw, ptr, ids, w, 10.0, 10)
     assert rel_err(c.query(q, qw, 10.0, 10)[0], want).max() <= FP32_RTOL
+
+
+# ---- step mode (iteration-level batching) ----
+
+@pytest.mark.parametrize("step_iters,max_batch,words", [(1, 1, 0), (4, 6, 0), (7, 16, 0), (5, 16, 120)])
+def test_step_mode_equals_single_bitwise(ragged, wmd, step_iters, max_batch, words):
+    """Queries that join and leave between steps, each at its own iteration
+    count (lambdas on both sides of the K .* M switch, 0 iterations, counts
+    that are and are not multiples of the step), give wmd_query's results bit
+    for bit, residuals included."""
+    (vecs, ptr, ids, w), c = ragged
+    qs = mixed_queries(vecs.shape[0], 30, seed=100 + step_iters, hi=260)
+    params = [(10.0, 12), (0.25, 5), (50.0, 0), (1.0, 9), (10.0, 1), (3.0, 14)] * 5
+    with wmd.Server(c, step_iters=step_iters, max_batch=max_batch, want_resid=True, max_batch_words=words) as s:
+        tickets = [s.submit(q, qw, lam, t) for (q, qw), (lam, t) in zip(qs, params)]
+        served = [s.wait(t) for t in tickets]
+        st = s.stats()
+    assert st["submitted"] == st["completed"] == len(qs)
+    assert 0 < st["mean_batch"] <= max_batch
+    for (q, qw), (lam, t), (d, r) in zip(qs, params, served):
+        d1, r1 = c.query(q, qw, lam, t, resid=True)
+        np.testing.assert_array_equal(d, d1)
+        np.testing.assert_array_equal(r, r1)
+    q, qw = qs[0]
+    want, _ = sinkhorn_wmd_sparse(vecs, q, qw, ptr, ids, w, 10.0, 12)
+    assert rel_err(served[0][0], want).max() <= FP32_RTOL
+
+
+def test_step_mode_log_domain(ragged, wmd):
+    """Column-shifted K (each query's row minima in its own region) at a large
+    lambda, stepped: equal to the single call."""
+    (vecs, ptr, ids, w), c = ragged
+    qs = mixed_queries(vecs.shape[0], 10, seed=41, hi=120)
+    with wmd.Server(c, step_iters=3, max_batch=5, log_domain=True) as s:
+        tickets = [s.submit(q, qw, 200.0, 8) for q, qw in qs]
+        for (q, qw), t in zip(qs, tickets):
+            np.testing.assert_array_equal(s.wait(t)[0], c.query(q, qw, 200.0, 8, log_domain=True)[0])
+
+
+def test_step_mode_short_query_overtakes_long(ragged, wmd):
+    """A short query admitted beside a long one finishes while the long one is
+    still iterating (it does not wait for the long query's batch)."""
+    (vecs, ptr, ids, w), c = ragged
+    rng = np.random.default_rng(8)
+    ql = rng.choice(vecs.shape[0], 200, replace=False).astype(np.int32)
+    qs = rng.choice(vecs.shape[0], 6, replace=False).astype(np.int32)
+    ones = lambda q: np.ones(q.size, np.float32)
+    with wmd.Server(c, step_iters=4, max_batch=4) as s:
+        t_long = s.submit(ql, ones(ql), 10.0, 20000)
+        t_short = s.submit(qs, ones(qs), 10.0, 3)
+        np.testing.assert_array_equal(s.wait(t_short)[0], c.query(qs, ones(qs), 10.0, 3)[0])
+        with pytest.raises(wmd.WmdError) as e:
+            s.wait(t_long, timeout_us=0)
+        assert e.value.code == wmd.WMD_ETIMEDOUT
+        np.testing.assert_array_equal(s.wait(t_long)[0], c.query(ql, ones(ql), 10.0, 20000)[0])
+
+
+def test_step_mode_budget_and_options(ragged, wmd):
+    (vecs, ptr, ids, w), c = ragged
+    U, N = c.info["U"], c.info["N"]
+    rng = np.random.default_rng(4)
+
+    def query(m):
+        return rng.choice(vecs.shape[0], m, replace=False).astype(np.int32), np.ones(m, np.float32)
+
+    # a query's region: K block (U x ldk) + x (N x ldk) + results; the budget
+    # holds regions for about 300 query words in flight
+    budget = 4 * (U + N) * 300 + (1 << 16)
+    small, mid, big = query(8), query(200), query(700)
+    with wmd.Server(c, step_iters=4, hbm_budget_bytes=budget, max_batch=8) as s:
+        with pytest.raises(wmd.WmdError) as e:
+            s.submit(*big, 10.0, 5)
+        assert e.value.code == wmd.WMD_ENOMEM
+        tickets = [s.submit(*mid, 10.0, 9) for _ in range(3)] + [s.submit(*small, 10.0, 9) for _ in range(6)]
+        ref_mid, ref_small = c.query(*mid, 10.0, 9)[0], c.query(*small, 10.0, 9)[0]
+        for i, t in enumerate(tickets):
+            np.testing.assert_array_equal(s.wait(t)[0], ref_mid if i < 3 else ref_small)
+        assert s.stats()["completed"] == len(tickets)
+    for kw in ({"step_iters": -1}, {"step_iters": 2, "tol": 1e-3}, {"step_iters": 2, "lse": True},
+               {"step_iters": 2, "iters_per_launch": 3}):
+        with pytest.raises(wmd.WmdError) as e:
+            wmd.Server(c, **kw)
+        assert e.value.code == wmd.WMD_EINVAL, kw
