@@ -67,6 +67,11 @@ PEAK_FP64_VALU_TFLOPS = 78.6     # MI355X FP64 vector
 # x 16 lanes / 4 x 2.4 GHz
 PEAK_EXP_TPS = 256 * 4 * 16 / 4 * 2.4e9 / 1e12
 MIN_WARMUP_S = 0.3
+# server step mode (iteration-level batching): iterations per step, queries
+# and query words in flight
+STEP_ITERS = 5
+STEP_BATCH = 16
+STEP_WORDS = 1024
 
 
 def parse():
@@ -100,6 +105,9 @@ def parse():
     p.add_argument("--streams", type=int, default=2, help="server streams (batches in flight)")
     p.add_argument("--batch-words", type=int, default=512, help="server cap on query words per batch")
     p.add_argument("--hbm-budget-gib", type=float, default=16.0)
+    p.add_argument("--step-iters", type=int, default=STEP_ITERS, help="server step mode: iterations per step")
+    p.add_argument("--step-batch", type=int, default=STEP_BATCH, help="server step mode: queries in flight")
+    p.add_argument("--step-words", type=int, default=STEP_WORDS, help="server step mode: query words in flight")
     return p.parse_args()
 
 
@@ -352,6 +360,19 @@ def batch_section(wmd, corpus, reps: int = 3) -> dict:
         st = srv.stats()
         out["served"] = {"ms": t_srv * 1e3, "doc_iters_per_s": work / t_srv, "mean_batch": st["mean_batch"],
                          "max_batch": 16, "streams": 2, "vs_back_to_back": t_b2b / t_srv}
+    step_kw = dict(step_iters=STEP_ITERS, max_batch=STEP_BATCH, max_batch_words=STEP_WORDS)
+    with wmd.Server(corpus, **step_kw) as srv:
+        def closed_step():
+            ts = [srv.submit(q, w, lam, iters) for q, w in qs]
+            return [srv.wait(t)[0] for t in ts]
+        got = closed_step()
+        assert all(np.array_equal(g, r) for g, r in zip(got, ref)), "served (step mode) != plain"
+        t_step = best(closed_step)
+        st = srv.stats()
+        out["served_step"] = {"ms": t_step * 1e3, "doc_iters_per_s": work / t_step,
+                              "mean_queries_per_step": st["mean_batch"], "step_iters": STEP_ITERS,
+                              "max_queries_in_flight": STEP_BATCH, "max_words_in_flight": STEP_WORDS,
+                              "vs_back_to_back": t_b2b / t_step}
     # open loop: Poisson arrivals at 70% of the back-to-back capacity, the same
     # sequence for both; each path warmed on the first 64 queries first
     rate = 0.7 * B / t_b2b
@@ -359,16 +380,20 @@ def batch_section(wmd, corpus, reps: int = 3) -> dict:
     arr = np.cumsum(np.random.default_rng(7).exponential(1.0 / rate, size=n_open))
     stream = [qs[i % B] for i in range(n_open)]
     lat_plain, _ = open_loop_plain(lambda qa: corpus.query(qa[0], qa[1], lam, iters), stream, arr)
-    with wmd.Server(corpus, max_batch=16, max_inflight=2) as srv:
-        for t in [srv.submit(q, w, lam, iters) for q, w in qs]:
-            srv.wait(t)
-        srv.reset_stats()
-        open_loop_served(srv, stream, arr, lam, iters)
-        st = srv.stats()
+    served = {}
+    for name, kw in (("served", dict(max_batch=16, max_inflight=2)), ("served_step", step_kw)):
+        with wmd.Server(corpus, **kw) as srv:
+            for t in [srv.submit(q, w, lam, iters) for q, w in qs]:
+                srv.wait(t)
+            srv.reset_stats()
+            open_loop_served(srv, stream, arr, lam, iters)
+            served[name] = srv.stats()
     out["open_loop"] = {"qps": rate, "queries": n_open,
                         "plain_latency_ms": pct(lat_plain),
-                        "served_latency_ms": server_latency(st),
-                        "served_mean_batch": st["mean_batch"]}
+                        "served_latency_ms": server_latency(served["served"]),
+                        "served_mean_batch": served["served"]["mean_batch"],
+                        "served_step_latency_ms": server_latency(served["served_step"]),
+                        "served_step_mean_queries_per_step": served["served_step"]["mean_batch"]}
     return out
 
 
@@ -461,11 +486,13 @@ def precision_section(wmd, steps: int = 400, sample_docs: int = 400) -> dict:
 
 
 def served_stream(wmd, wl, nq: int, rates=None, sample_queries: int = 6, sample_docs: int = 150,
-                  budget: int = 16 << 30, max_batch: int = 16, streams: int = 2, batch_words: int = 512) -> dict:
+                  budget: int = 16 << 30, max_batch: int = 16, streams: int = 2, batch_words: int = 512,
+                  step_iters: int = STEP_ITERS, step_batch: int = STEP_BATCH, step_words: int = STEP_WORDS) -> dict:
     """Served stream on the large corpus: plain FP32 synchronous calls vs the
-    server in FP32 (same accuracy) vs the server with BF16 distances, same
-    queries and Poisson arrival times; served results checked bitwise against
-    plain calls (FP32) and against the FP64 oracle on sampled documents."""
+    server in FP32 (same accuracy) vs the server with BF16 distances, each in
+    batch mode and in step mode (iteration-level batching), same queries and
+    Poisson arrival times; served results checked bitwise against plain calls
+    (FP32) and against the FP64 oracle on sampled documents."""
     from oracle import sinkhorn_wmd_sparse
     from paper_2005_06727_amd import synth
     sp = wl.spec
@@ -478,7 +505,11 @@ def served_stream(wmd, wl, nq: int, rates=None, sample_queries: int = 6, sample_
     keep = set(int(i) for i in np.argsort(lens)[np.linspace(0, nq - 1, sample_queries).astype(int)])
     work = nq * N * iters
     kw = dict(hbm_budget_bytes=budget, max_batch=max_batch, max_inflight=streams, max_batch_words=batch_words)
-    paths = {"plain_fp32": None, "served_fp32": wmd.WMD_DIST_FP32, "served_bf16": wmd.WMD_DIST_BF16}
+    kws = dict(hbm_budget_bytes=budget, max_batch=step_batch, max_batch_words=step_words, step_iters=step_iters)
+    paths = {"served_fp32": dict(kw, precision=wmd.WMD_DIST_FP32),
+             "served_bf16": dict(kw, precision=wmd.WMD_DIST_BF16),
+             "served_step_fp32": dict(kws, precision=wmd.WMD_DIST_FP32),
+             "served_step_bf16": dict(kws, precision=wmd.WMD_DIST_BF16)}
 
     for q, w in qs[:8]:
         corpus.query(q, w, lam, iters)
@@ -491,8 +522,8 @@ def served_stream(wmd, wl, nq: int, rates=None, sample_queries: int = 6, sample_
         if i in keep:
             kept["plain_fp32"][i] = d
     closed["plain_fp32"] = nq / (time.perf_counter() - t)
-    for name in ("served_fp32", "served_bf16"):
-        with wmd.Server(corpus, precision=paths[name], **kw) as srv:
+    for name in paths:
+        with wmd.Server(corpus, **paths[name]) as srv:
             for tk in [srv.submit(q, w, lam, iters) for q, w in qs[:32]]:
                 srv.wait(tk)
             t = time.perf_counter()
@@ -503,11 +534,12 @@ def served_stream(wmd, wl, nq: int, rates=None, sample_queries: int = 6, sample_
                 if i in keep:
                     kept[name][i] = d
             closed[name] = nq / (time.perf_counter() - t)
-    same = all(np.array_equal(kept["served_fp32"][i], kept["plain_fp32"][i]) for i in keep)
+    same = {name: all(np.array_equal(kept[name][i], kept["plain_fp32"][i]) for i in keep)
+            for name in ("served_fp32", "served_step_fp32")}
     # accuracy on sampled queries x sampled documents
     docs = np.linspace(0, N - 1, sample_docs).astype(np.int64)
     sptr, sids, sw = synth.subcorpus(wl.doc_ptr, wl.word_ids, wl.weights, docs)
-    errs = {"served_fp32": [], "served_bf16": []}
+    errs = {name: [] for name in paths}
     for i in sorted(keep):
         q, w = qs[i]
         want, _ = sinkhorn_wmd_sparse(wl.vecs, q, w, sptr, sids, sw, lam, iters)
@@ -522,8 +554,8 @@ def served_stream(wmd, wl, nq: int, rates=None, sample_queries: int = 6, sample_
         run = {"qps": qps, "load_of_served_bf16_capacity": qps / X}
         lat, span = open_loop_plain(lambda qa: corpus.query(qa[0], qa[1], lam, iters), qs, arr)
         run["plain_fp32"] = {"latency_ms": pct(lat), "doc_iters_per_s": work / span}
-        for name in ("served_fp32", "served_bf16"):
-            with wmd.Server(corpus, precision=paths[name], **kw) as srv:
+        for name in paths:
+            with wmd.Server(corpus, **paths[name]) as srv:
                 for tk in [srv.submit(q, w, lam, iters) for q, w in qs[:16]]:
                     srv.wait(tk)
                 srv.reset_stats()
@@ -539,9 +571,12 @@ def served_stream(wmd, wl, nq: int, rates=None, sample_queries: int = 6, sample_
                         f"U={info['U']}, lambda={lam}, {iters} iterations",
             "server": {"hbm_budget_bytes": budget, "max_batch": max_batch, "streams": streams,
                        "max_batch_words": batch_words},
+            "server_step_mode": {"hbm_budget_bytes": budget, "step_iters": step_iters,
+                                 "max_queries_in_flight": step_batch, "max_words_in_flight": step_words},
             "closed_loop_qps": closed,
             "closed_loop_doc_iters_per_s": {k: v * N * iters for k, v in closed.items()},
-            "served_fp32_equals_plain_fp32_bitwise": bool(same),
+            "served_fp32_equals_plain_fp32_bitwise": bool(same["served_fp32"]),
+            "served_step_fp32_equals_plain_fp32_bitwise": bool(same["served_step_fp32"]),
             "rel_error_vs_fp64_oracle": {k: rel_stats(np.concatenate(v)) for k, v in errs.items()},
             "error_sample": f"{len(keep)} queries across the v_r range x {docs.size} documents",
             "open_loop": runs}
@@ -555,7 +590,8 @@ def serve_main(args):
     wl = synth.make(args.serve, n_queries=args.queries)
     res = served_stream(wmd, wl, args.queries, [args.qps] if args.qps > 0 else None,
                         budget=int(args.hbm_budget_gib * (1 << 30)), max_batch=args.max_batch,
-                        streams=args.streams, batch_words=args.batch_words)
+                        streams=args.streams, batch_words=args.batch_words, step_iters=args.step_iters,
+                        step_batch=args.step_batch, step_words=args.step_words)
     top = res["open_loop"][-1]
     line = {"metric": "served doc*iters/s + p50/p99 query latency", "value": top["served_bf16"]["doc_iters_per_s"],
             "unit": "doc*iters/s", "n_gpus": 1, "higher_is_better": True,

@@ -316,15 +316,16 @@ int wmd_timing_get(wmd_corpus* corpus, wmd_timing* out);
  * wmd_query returns for it with the same options: a document's computation
  * does not depend on the rest of the batch.
  *
- * Step mode (step_iters > 0): iteration-level continuous batching on one
- * stream.  Each admitted query holds its own region of the budget (K block,
- * iterate x, results: about 4 (U + N) ldk bytes) until it completes, and at
- * most max_batch queries are in flight.  The worker enqueues steps (at most
- * two ahead): a step runs the distance kernel of the queries admitted into
- * it, then one Sinkhorn launch per shape class over every in-flight query,
- * each advancing step_iters iterations from its own count (with the final
- * step once it reaches its iteration count), then downloads the results of
- * the queries that finished.  Queries join and leave between steps, so a
+ * Step mode (step_iters > 0): iteration-level continuous batching.  Each
+ * admitted query holds its own region of the budget (K block, iterate x,
+ * results: about 4 (U + N) ldk bytes) until it completes, and at most
+ * max_batch queries are in flight.  The worker enqueues steps (at most two
+ * ahead): a step runs the distance kernel of the queries admitted into it
+ * (on a second stream, beside the previous step), then one Sinkhorn launch
+ * per shape class over every in-flight query, each advancing step_iters
+ * iterations from its own count (with the final step once it reaches its
+ * iteration count), then downloads the results of the queries that
+ * finished.  Queries join and leave between steps, so a
  * short query does not wait for a long one to finish.  Results are bitwise
  * those of wmd_query (the iterate is kept in FP32 between launches, as in a
  * call with iters_per_launch).  Needs tol = 0, lse = 0, iters_per_launch = 0;
