@@ -834,7 +834,8 @@ def main():
     }
     dom = "sinkhorn_fused" if sink_s >= dist_s else "dist_gemm"
     kd = kernels[dom]
-    traffic = counter_traffic(dom, ["k_sinkhorn.hip"] if dom == "sinkhorn_fused" else ["k_dist.hip"])
+    traffic = counter_traffic(dom, ["k_sinkhorn.hip" if dom == "sinkhorn_fused" else "k_dist.hip", "wmd_device.h",
+                                    "wmd_internal.h"])
     roofline = {"kernel": dom, "bound": kd["bound"], "achieved": kd["achieved"], "peak": kd["peak"],
                 "unit": kd["unit"], "frac": kd["frac"], "traffic": traffic,
                 "time_source": f"HIP events holding the kernel dispatches' own start and end "

@@ -546,8 +546,6 @@ int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wm
         a.scw = dc.scw;
         a.sdoc = dc.sdoc;
         a.zpad = dc.zpad;
-        a.pent = dc.pent;
-        a.pad_d0 = (int32_t)dc.pad_d0;
         a.it_begin = 0;
         a.it_count = max_iters;
         a.final_step = 1;
@@ -563,8 +561,6 @@ int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wm
         a.scw = dc.scw;
         a.sdoc = dc.sdoc;
         a.zpad = dc.zpad;
-        a.pent = dc.pent;
-        a.pad_d0 = (int32_t)dc.pad_d0;
         a.it_begin = it0;
         a.it_count = per_launch;
         a.final_step = (int64_t)it0 + per_launch >= max_iters ? 1 : 0;
@@ -645,7 +641,6 @@ static void corpus_free(wmd_corpus* c) {
     dfree(d.scw);
     dfree(d.sdoc);
     dfree(d.zpad);
-    dfree(d.pent);
     for (int sl = 0; sl < kWorkSlots; ++sl) free_workspace(c->ws[sl]);
     free_staging(c->stage);
     for (int i = 0; i < wmd_corpus::kTimingSlots; ++i)
@@ -748,8 +743,6 @@ int wmd_corpus_create(const float* vecs, int64_t V, int32_t dim, const int64_t* 
     c->h_sorted_len.push_back(0);
     c->d_tile = 0;
     while (c->d_tile < N && slen[c->d_tile] > kTileMaxDoc) ++c->d_tile;
-    d.pad_d0 = c->d_tile;
-    const size_t npent = (size_t)(N - c->d_tile) * kPadDocWidth;
 
     hipError_t e = hipSuccess;
     auto bail = [&](hipError_t err, const char* what) {
@@ -773,8 +766,7 @@ int wmd_corpus_create(const float* vecs, int64_t V, int32_t dim, const int64_t* 
         (e = dalloc(&d.act_norm, (size_t)U)) != hipSuccess || (e = dalloc(&d.act_word, (size_t)U)) != hipSuccess ||
         (e = dalloc(&d.sptr, (size_t)N + 1)) != hipSuccess || (e = dalloc(&d.scol, (size_t)nnz)) != hipSuccess ||
         (e = dalloc(&d.scw, (size_t)nnz)) != hipSuccess || (e = dalloc(&d.sdoc, (size_t)N)) != hipSuccess ||
-        (e = dalloc(&d.zpad, (size_t)kZpadFloats)) != hipSuccess ||
-        (npent > 0 && (e = dalloc(&d.pent, npent)) != hipSuccess))
+        (e = dalloc(&d.zpad, (size_t)kZpadFloats)) != hipSuccess)
         return bail(e, "corpus: device allocation");
     if (opt.bf16) {
         if ((e = dalloc(&d.act_bf16, (size_t)U * ldv)) != hipSuccess ||
@@ -796,16 +788,14 @@ int wmd_corpus_create(const float* vecs, int64_t V, int32_t dim, const int64_t* 
         return bail(e, "corpus: upload");
     if ((e = launch_gather_rows(d.vecs, d.act_word, d.act, U, d.ldv, s)) != hipSuccess ||
         (e = launch_prep_norms(d.act, U, d.ldv, d.act_norm, s)) != hipSuccess ||
-        (e = launch_prep_docs(d.sptr, d.scw, d.scw, N, s)) != hipSuccess ||
-        (e = launch_prep_doc_pad(d.sptr, d.scol, d.scw, d.pad_d0, N, kPadDocWidth, d.pent, s)) != hipSuccess)
+        (e = launch_prep_docs(d.sptr, d.scw, d.scw, N, s)) != hipSuccess)
         return bail(e, "corpus: preparation kernels");
     if (opt.bf16 && (e = launch_prep_bf16(d.act, d.act_bf16, d.act_norm_bf16, U, d.ldv, s)) != hipSuccess)
         return bail(e, "corpus: BF16 preparation");
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return bail(e, "corpus: preparation");
     c->device_bytes = (int64_t)((V + U) * ldv * sizeof(float) + U * (sizeof(float) + sizeof(int32_t)) +
                                 (N + 1 + N) * sizeof(int32_t) + nnz * (sizeof(int32_t) + sizeof(float)) +
-                                kZpadFloats * sizeof(float) + npent * sizeof(int2) +
-                                (opt.bf16 ? U * (ldv * sizeof(uint16_t) + sizeof(float)) : 0));
+                                kZpadFloats * sizeof(float) + (opt.bf16 ? U * (ldv * sizeof(uint16_t) + sizeof(float)) : 0));
     *out = c;
     return WMD_OK;
 }

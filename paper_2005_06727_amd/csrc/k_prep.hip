@@ -1,7 +1,5 @@
 // Corpus preparation kernels: row norms, BF16 copies, per-document
 // normalisation of the histogram weights (columns of c sum to one, Sec. 4).
-#include <algorithm>
-
 #include "wmd_internal.h"
 
 namespace wmd {
@@ -65,20 +63,6 @@ __global__ void k_doc_normalise(const int32_t* __restrict__ ptr, const float* w,
     for (int p = b; p < e; ++p) cw[p] = (float)((double)w[p] / s);
 }
 
-// Row entries of the documents [d0, N) (each at most `width` words) at a fixed
-// stride of `width`: entry (d - d0) * width + i holds (word index, weight bits)
-// of the document's row i, and (0, 0) beyond its length.
-__global__ void k_doc_pad(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
-                          const float* __restrict__ cw, int64_t d0, int64_t N, int width, int2* __restrict__ out) {
-    const int64_t total = (N - d0) * width;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t d = d0 + e / width;
-        const int i = (int)(e % width);
-        const int b = ptr[d], n = ptr[d + 1] - b;
-        out[e] = i < n ? make_int2(col[b + i], __float_as_int(cw[b + i])) : make_int2(0, 0);
-    }
-}
-
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -101,15 +85,6 @@ hipError_t launch_prep_bf16(const float* src, uint16_t* dst, float* norms, int64
 hipError_t launch_prep_docs(const int32_t* ptr, const float* w, float* cw, int64_t N, hipStream_t s) {
     if (N <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_doc_normalise, dim3(blocks_for(N, 256)), dim3(256), 0, s, ptr, w, cw, N);
-    return hipGetLastError();
-}
-
-hipError_t launch_prep_doc_pad(const int32_t* ptr, const int32_t* col, const float* cw, int64_t d0, int64_t N,
-                               int width, int2* out, hipStream_t s) {
-    if (N <= d0) return hipSuccess;
-    const int64_t total = (N - d0) * width;
-    hipLaunchKernelGGL(k_doc_pad, dim3((unsigned)std::min<int64_t>(blocks_for(total, 256), 8192)), dim3(256), 0, s,
-                       ptr, col, cw, d0, N, width, out);
     return hipGetLastError();
 }
 

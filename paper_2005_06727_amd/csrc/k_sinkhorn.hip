@@ -297,7 +297,7 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
                                           const int rs, const int n, const int m, const int ldk, const int a,
                                           const int b, const int tl, const int wi, const int team, const int kb,
                                           const int it_end, const int my_end, float* s_part, double* s_red,
-                                          float* s_rho, float* s_x, const int2 (&pe)[(W == 1) ? P : 1]) {
+                                          float* s_rho, float* s_x) {
     constexpr int T = R * C;
     constexpr int Q4 = Q / 4;
     // The SpMM's column sums are reduce-scattered over the R lanes of a column
@@ -341,17 +341,20 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
     float cval[PN];
     float A[PN][Q];
     if constexpr (W == 1) {
-        // Branch-free loads of the rows of Kt, all in flight at once (a branch
-        // per row makes the compiler wait for each row's loads before issuing
-        // the next); the row entries came with the document's rank.  A row
-        // beyond the document reads its Kt values from the zero block, whose
-        // first four values are (1, 0, 0, 0); a column group beyond m reads
-        // zeros there too.  Choosing the address instead of the loaded value
-        // keeps the loads' destinations in A (no second set of registers).
+        // Branch-free loads, all in flight at once (a branch per row makes the
+        // compiler wait for each row's loads before issuing the next): the
+        // indices and weights of the lane's rows first, then the rows of Kt.
+        // A row beyond the document reads index 0 (present: every document has
+        // a word) and its Kt values from the zero block, whose first four
+        // values are (1, 0, 0, 0); a column group beyond m reads zeros there
+        // too.  Choosing the address instead of the loaded value keeps the
+        // loads' destinations in A (no second set of registers).
 #pragma unroll
         for (int p = 0; p < PN; ++p) {
-            col[p] = pe[p].x;
-            cval[p] = __int_as_float(pe[p].y);
+            const int i = a + R * p;
+            const int e = (valid && i < n) ? rs + i : 0;
+            col[p] = g.scol[e];
+            cval[p] = g.scw[e];
         }
         const auto zp = gmem(g.zpad);
 #pragma unroll
@@ -735,16 +738,6 @@ __global__ __launch_bounds__(256, (W > 1) ? 1 : (P >= 16) ? 2 : (P <= 4) ? 5 : 3
     // loads need no guard (a guarded load would be waited for inside its branch)
     const int rs = g.sptr[d];
     const int re = g.sptr[d + 1];
-    // the one-wave teams' row entries (index, weight) of rows a + R p, read
-    // from the padded copy, whose address needs the document's rank only: they
-    // are in flight together with the row pointers, before the wait for n
-    static_assert(R * P <= kPadDocWidth, "a tile's rows fit the padded entries");
-    int2 pe[(W == 1) ? P : 1];
-    if constexpr (W == 1) {
-        const auto pp = gmem(g.pent) + (int64_t)(d - g.pad_d0) * kPadDocWidth + a;
-#pragma unroll
-        for (int p = 0; p < P; ++p) pe[p] = ld2i(pp + R * p);
-    }
     const int n = valid ? re - rs : 0;
     const int kb = (wi * C + b) * Q;
 
@@ -773,7 +766,7 @@ __global__ __launch_bounds__(256, (W > 1) ? 1 : (P >= 16) ? 2 : (P <= 4) ? 5 : 3
     }
     sink_dispatch<R, C, P, Q, W, (P >= 16) ? 2 : 1, (P >= 16) ? 2 : 1>(
         pr, g, qp, valid, d, rs, n, m, ldk, a, b, tl, wi, team, kb, it_end, my_end, s_part, s_red, s_rho,
-        s_x + (XL ? (team * W + wi) * XTEAM : 0), pe);
+        s_x + (XL ? (team * W + wi) * XTEAM : 0));
 }
 
 // Any size: one 256-thread block per (query, document); the K block is

@@ -472,8 +472,6 @@ int enqueue_step(wmd_server* S, int k, std::vector<Active>& act, std::vector<Act
         g.scw = dc.scw;
         g.sdoc = dc.sdoc;
         g.zpad = dc.zpad;
-        g.pent = dc.pent;
-        g.pad_d0 = (int32_t)dc.pad_d0;
         g.it_begin = 0;
         g.it_count = iters_step;
         g.final_step = 0;

@@ -14,7 +14,7 @@ namespace wmd {
 
 constexpr int kMaxQueryWords = 4096;   // streaming kernel LDS: 3 floats per query word
 constexpr int kMaxDocWords = 16384;    // streaming kernel LDS: 1 float per document word
-constexpr int kTileMaxDoc = kPadDocWidth;   // documents up to this length use the register tiles
+constexpr int kTileMaxDoc = 64;        // documents up to this length use the register tiles
 constexpr float kKmFromKMinLambda = 0.5f;  // from this lambda on, K .* M is rebuilt from K
 
 // Device buffers of one query call.  A corpus has kWorkSlots of them, used

@@ -24,11 +24,4 @@ __device__ __forceinline__ float4 ld4(WMD_GLOBAL const float* p) {
     return make_float4(v.x, v.y, v.z, v.w);
 }
 
-typedef int gv2i __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ int2 ld2i(WMD_GLOBAL const int2* p) {
-    const gv2i v = *(WMD_GLOBAL const gv2i*)p;
-    return make_int2(v.x, v.y);
-}
-
 }  // namespace wmd

@@ -55,14 +55,7 @@ struct DevCorpus {
     float* scw = nullptr;           // nnz: normalised weight c_ij
     int32_t* sdoc = nullptr;        // N: input id of each sorted document
     float* zpad = nullptr;          // kZpadFloats: 1, 0, 0, ...: source of padding loads
-    // row entries (word index, weight bits) of the sorted documents [pad_d0, N)
-    // at a stride of kPadDocWidth, zero beyond each document's length: a
-    // document's rows are addressed from its rank alone
-    int2* pent = nullptr;
-    int64_t pad_d0 = 0;
 };
-
-constexpr int kPadDocWidth = 64;
 
 // Floats in the corpus's padding block (1 followed by zeros), read by the
 // Sinkhorn kernels in place of the rows and columns beyond a document or query.
@@ -86,10 +79,6 @@ struct SinkArgs {
     // nonzero: the launch has one query whose record is qd[0]; qlist is not
     // read, so the record's load does not wait for a load of qlist
     int32_t single = 0;
-    // the corpus's padded row entries and the rank of their first document
-    // (the register tiles read rows from them; their documents are >= pad_d0)
-    const int2* pent = nullptr;
-    int32_t pad_d0 = 0;
     // nonzero: each query runs it_count iterations from its own it_base (its
     // record), with the final step when that reaches its iteration count;
     // it_begin and final_step are then ignored
@@ -123,8 +112,6 @@ hipError_t launch_prep_norms(const float* rows, int64_t nrows, int ldv, float* n
 hipError_t launch_prep_bf16(const float* src, uint16_t* dst, float* norms, int64_t nrows, int ldv,
                             hipStream_t s);
 hipError_t launch_prep_docs(const int32_t* ptr, const float* w, float* cw, int64_t N, hipStream_t s);
-hipError_t launch_prep_doc_pad(const int32_t* ptr, const int32_t* col, const float* cw, int64_t d0, int64_t N,
-                               int width, int2* out, hipStream_t s);
 // Parameter blocks up to kUploadMaxBytes are uploaded as kernel arguments, in
 // chunks of kUploadChunkBytes (one small launch each).
 constexpr int kUploadChunkBytes = 2048;
