@@ -524,7 +524,7 @@ int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wm
     }
     const int32_t* dqg = reinterpret_cast<const int32_t*>(dp + off_qg);
     if (opt.lse) e = launch_dist_lse(dc, dq, dqg, B, (int)sum_ldk, stream);
-    else if (narrow) e = launch_dist_narrow(dc, hq[0], dq, hp, pbytes, off_id, dp, bf16, stream);
+    else if (narrow) e = launch_dist_narrow(dc, hq[0], hp, pbytes, off_id, dp, bf16, stream);
     else e = launch_dist(dc, dq, dqg, B, (int)sum_ldk, bf16, opt.log_domain, stream);
     if (e != hipSuccess) return hip_fail(e, "query: distance kernel launch");
     ++launches;

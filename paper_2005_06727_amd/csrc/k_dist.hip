@@ -486,10 +486,48 @@ __global__ __launch_bounds__(256) void k_dist_narrow(NarrowArgs a) {
             }
     }
 
-    // epilogue (the same arithmetic as the general kernel's)
+    // epilogue (the same arithmetic as the general kernel's).  Lane (lr, lg)
+    // holds rows 4 lg + r of columns 16 nb + lr: the wave has every column of
+    // its 16 rows, so the column shift's row minimum is a reduction over the
+    // 16 lanes of a row group, and K is written once (the general kernel needs
+    // atomics and a second pass, as a query's columns span several blocks).
+    float dv[2][4];
+    bool live[2][4];
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb) {
         const float qnj = sum_lane_groups(qn[nb]);
+        const int k = 16 * nb + lr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t gi = rbase + 4 * lg + r;
+            live[nb][r] = k < m && gi < a.U;
+            float d = INFINITY;
+            if (live[nb][r]) {
+                if (e_word[r] == qw[nb]) {
+                    d = 0.f;
+                } else {
+                    float d2 = e_norm[r] + qnj - 2.f * acc[nb][r];
+                    if (d2 < a.tau2) d2 = direct_d2(a.act + gi * ldv, a.vecs + (int64_t)qw[nb] * ldv, ldv);
+                    d = sqrtf(fmaxf(d2, 0.f));
+                }
+            }
+            dv[nb][r] = d;
+        }
+    }
+    float nmin[4] = {0.f, 0.f, 0.f, 0.f};
+    if (a.shift) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float t = fminf(dv[0][r], dv[1][r]);
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) t = fminf(t, __shfl_xor(t, o, 64));
+            nmin[r] = t;
+            const int64_t gi = rbase + 4 * lg + r;
+            if (lr == 0 && gi < a.U) a.nrow[gi] = t;
+        }
+    }
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
         const int k = 16 * nb + lr;
         if (k >= a.ldk) continue;
 #pragma unroll
@@ -497,27 +535,15 @@ __global__ __launch_bounds__(256) void k_dist_narrow(NarrowArgs a) {
             const int64_t gi = rbase + 4 * lg + r;
             if (gi >= a.U) continue;
             float* kt = a.Kt + gi * a.ldk + k;
-            if (k >= m) {
+            if (!live[nb][r]) {
                 *kt = 0.f;
                 if (a.km) a.KMt[gi * a.ldk + k] = 0.f;
                 continue;
             }
-            float d;
-            if (e_word[r] == qw[nb]) {
-                d = 0.f;
-            } else {
-                float d2 = e_norm[r] + qnj - 2.f * acc[nb][r];
-                if (d2 < a.tau2) d2 = direct_d2(a.act + gi * ldv, a.vecs + (int64_t)qw[nb] * ldv, ldv);
-                d = sqrtf(fmaxf(d2, 0.f));
-            }
-            if (a.shift) {
-                *kt = d;
-                atomicMin(reinterpret_cast<unsigned int*>(a.nrow + gi), __float_as_uint(d));
-            } else {
-                const float kv = expf(-a.lambda * d);
-                *kt = kv;
-                if (a.km) a.KMt[gi * a.ldk + k] = kv * d;
-            }
+            const float d = dv[nb][r];
+            const float kv = a.shift ? expf(-a.lambda * (d - nmin[r])) : expf(-a.lambda * d);
+            *kt = kv;
+            if (a.km) a.KMt[gi * a.ldk + k] = kv * d;
         }
     }
 }
@@ -536,11 +562,6 @@ __global__ __launch_bounds__(256) void k_shift_exp(const QueryDev* qd, int64_t U
         q.Kt[e] = kv;
         if (!q.km_from_k) q.KMt[e] = kv * d;
     }
-}
-
-__global__ __launch_bounds__(256) void k_fill_inf(float* p, int64_t n) {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
-        p[e] = INFINITY;
 }
 
 // The row-minimum arrays of B queries (wherever each lies) set to +inf, query
@@ -595,7 +616,7 @@ bool dist_narrow_fits(const DevCorpus& c, int bf16, int B, int ncols, size_t pby
            pbytes % 4 == 0 && (c.U + TR - 1) / TR <= INT32_MAX;
 }
 
-hipError_t launch_dist_narrow(const DevCorpus& c, const QueryDev& hq, const QueryDev* qd_dev, const void* blob,
+hipError_t launch_dist_narrow(const DevCorpus& c, const QueryDev& hq, const void* blob,
                               size_t pbytes, size_t off_id, void* params_dev, int bf16, hipStream_t s) {
     NarrowArgs a;
     a.act = c.act;
@@ -621,11 +642,6 @@ hipError_t launch_dist_narrow(const DevCorpus& c, const QueryDev& hq, const Quer
     std::memset(a.blob, 0, sizeof a.blob);
     std::memcpy(a.blob, blob, pbytes);
     hipError_t e;
-    if (hq.shift) {
-        if ((e = launch_kernel(k_fill_inf, dim3((unsigned)std::min<int64_t>((c.U + 255) / 256, 4096)), dim3(256), 0,
-                               s, hq.nrow, c.U)) != hipSuccess)
-            return e;
-    }
     const int nc = c.ldv * (bf16 ? 2 : 4) / 128;
     const unsigned blocks = (unsigned)((c.U + TR - 1) / TR);
 #define WMD_NARROW(K)                                                                        \
@@ -639,9 +655,7 @@ hipError_t launch_dist_narrow(const DevCorpus& c, const QueryDev& hq, const Quer
         default: return hipErrorInvalidValue;
     }
 #undef WMD_NARROW
-    if (e != hipSuccess || !hq.shift) return e;
-    return launch_kernel(k_shift_exp, dim3((unsigned)std::min<int64_t>((c.U * 32 + 255) / 256, 2048), 1u), dim3(256),
-                         0, s, qd_dev, c.U);
+    return e;
 }
 
 }  // namespace wmd

@@ -136,9 +136,10 @@ hipError_t launch_topk(const double* dist, int64_t n, int k, void* scratch, size
                        double* res_dist, hipStream_t s);
 // K1 for one short query whose parameter block (at most kUploadChunkBytes, host
 // image with device pointers) travels as kernel arguments; block 0 stores it
-// at params_dev for the launches that follow.  hq: the query's fields.
+// at params_dev for the launches that follow.  hq: the query's fields.  One
+// launch, the column shift included.
 bool dist_narrow_fits(const DevCorpus& c, int bf16, int B, int ncols, size_t pbytes);
-hipError_t launch_dist_narrow(const DevCorpus& c, const QueryDev& hq, const QueryDev* qd_dev, const void* blob,
+hipError_t launch_dist_narrow(const DevCorpus& c, const QueryDev& hq, const void* blob,
                               size_t pbytes, size_t off_id, void* params_dev, int bf16, hipStream_t s);
 
 // Fused Sinkhorn iterations + final WMD step.  `shape` selects the register
