@@ -98,12 +98,25 @@ __device__ __forceinline__ int query_of(const int32_t* kofs, int B, int c) {
 }
 
 // Epilogue of a wave's sub-tile: lane (lr, lg) holds G[row 16 t + 4 lg + r]
-// [column 16 nb + lr] of the rows from rbase and columns from cbase.
+// [column 16 nb + lr] of the rows from rbase and columns from cbase.  With the
+// column shift, Kt receives d and the row minima go to each query's nrow by
+// atomics; when the wave's 32 columns belong to one query (always in a
+// one-query call, and for most columns of a batch), the minimum over them is
+// taken in the wave first and one lane per row does the atomic.
 template <int RT>
 __device__ __forceinline__ void epilogue(const DistArgs& a, const v4f (&acc)[RT][2], const float (&qn)[2],
                                          const int (&e_word)[RT][4], const float (&e_norm)[RT][4],
                                          const int64_t rbase, const int cbase, const int lr, const int lg) {
     const int ldv = a.ldv;
+    const int clast = min(cbase + 31, a.ncols - 1);
+    const int b0 = query_of(a.kofs, a.B, cbase);
+    const bool one_query = b0 == query_of(a.kofs, a.B, clast);
+    const bool shift = a.qd[b0].shift != 0;   // one option for every query of a call
+    float dmin[RT][4];
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dmin[t][r] = INFINITY;
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb) {
         const float qnj = sum_lane_groups(qn[nb]);
@@ -115,7 +128,7 @@ __device__ __forceinline__ void epilogue(const DistArgs& a, const v4f (&acc)[RT]
         const int m = q->m, ldk = q->ldk;
         const int qw = (k < m) ? q->qid[k] : -1;
         const float lam = q->lambda, tau2 = q->tau2;
-        const bool shift = q->shift != 0, km = !q->km_from_k;
+        const bool km = !q->km_from_k;
 #pragma unroll
         for (int t = 0; t < RT; ++t)
 #pragma unroll
@@ -139,12 +152,27 @@ __device__ __forceinline__ void epilogue(const DistArgs& a, const v4f (&acc)[RT]
                 if (shift) {
                     *kt = d;
                     // d >= 0, so the bit patterns order like the values
-                    atomicMin(reinterpret_cast<unsigned int*>(q->nrow + gi), __float_as_uint(d));
+                    if (one_query) dmin[t][r] = fminf(dmin[t][r], d);
+                    else atomicMin(reinterpret_cast<unsigned int*>(q->nrow + gi), __float_as_uint(d));
                 } else {
                     const float kv = expf(-lam * d);
                     *kt = kv;
                     if (km) q->KMt[gi * ldk + k] = kv * d;
                 }
+            }
+    }
+    if (shift && one_query) {
+        float* nrow = a.qd[b0].nrow;
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float v = dmin[t][r];
+#pragma unroll
+                for (int o = 1; o < 16; o <<= 1) v = fminf(v, __shfl_xor(v, o, 64));
+                const int64_t gi = rbase + 16 * t + 4 * lg + r;
+                if (lr == 0 && gi < a.U && v < INFINITY)
+                    atomicMin(reinterpret_cast<unsigned int*>(nrow + gi), __float_as_uint(v));
             }
     }
 }
@@ -329,7 +357,7 @@ __global__ __launch_bounds__(256) void k_dist(DistArgs a) {
     epilogue<RT>(a, acc, qn, e_word, e_norm, row0 + wr * 16 * RT, col0 + wc * 32, lr, lg);
 }
 
-// One short query (at most 32 columns), bound by reading the corpus rows.
+// One short query (at most 64 columns), bound by reading the corpus rows.
 // The query travels in the kernel arguments (its fields, and the whole
 // parameter block, which block 0 stores to device memory for the Sinkhorn
 // kernel), so no upload launch and no dependent metadata loads precede the
@@ -338,7 +366,10 @@ __global__ __launch_bounds__(256) void k_dist(DistArgs a) {
 // registers at once and the MFMAs consume them as they arrive.  Lane (lr, lg)
 // loads row lr, bytes [128 c + 32 lg, +32) of every 128-byte chunk c, so four
 // lanes read one full cache line; the general kernel uses the same k order,
-// so results do not depend on which kernel ran.
+// so results do not depend on which kernel ran.  A query of 33..64 columns
+// takes NP = 2 passes over the rows held in registers, the second with the
+// next 32 columns staged in the same LDS (their loads in flight during the
+// first pass), so the rows are read once.
 struct NarrowArgs {
     const float* act;
     const uint16_t* act16;
@@ -359,7 +390,7 @@ struct NarrowArgs {
     uint32_t blob[kUploadChunkBytes / 4];
 };
 
-template <bool BF16, int NC>
+template <bool BF16, int NC, int NP>
 __global__ __launch_bounds__(256) void k_dist_narrow(NarrowArgs a) {
     constexpr int SBB = NC * 128 + 16;   // LDS column stride (bytes): 8 lanes on distinct banks
     static_assert(4 + 64 * NC <= kZpadFloats, "padded loads stay inside the zero block");
@@ -372,36 +403,48 @@ __global__ __launch_bounds__(256) void k_dist_narrow(NarrowArgs a) {
     if (blockIdx.x == 0)
         for (int i = tid; i < a.pwords; i += 256) a.params[i] = a.blob[i];
 
-    // Every load is issued before the first wait, in three dependent rounds:
-    // the query ids (kernel arguments), then the query column pieces and the
-    // corpus rows.  Columns beyond m and rows beyond U read the zero block
-    // (the address is chosen, not the value, so nothing is selected later).
-    // Query columns -> LDS: 16-byte pieces, 32 columns x 8 NC pieces, NC per thread.
+    // Every load of the first pass is issued before the first wait, in three
+    // dependent rounds: the query ids (kernel arguments), then the query
+    // column pieces and the corpus rows.  Columns beyond m and rows beyond U
+    // read the zero block (the address is chosen, not the value, so nothing is
+    // selected later).  Query columns -> LDS: 16-byte pieces, 32 columns x
+    // 8 NC pieces, NC per thread.
     const auto zero = gmem(a.zpad) + 4;
-    int qrow[NC];
-#pragma unroll
-    for (int j = 0; j < NC; ++j) {
-        const int cl = (tid + 256 * j) / (8 * NC);
-        qrow[j] = (int32_t)a.blob[a.qid_word + (cl < m ? cl : 0)];
-    }
     uint4 v[NC];
+    auto load_cols = [&](int ps) {
+        int qrow[NC];
 #pragma unroll
-    for (int j = 0; j < NC; ++j) {
-        const int p = tid + 256 * j;
-        const int cl = p / (8 * NC), seg = p % (8 * NC);
-        const auto src = (cl < m) ? gmem(a.vecs) + (int64_t)qrow[j] * ldv : zero;
-        if constexpr (BF16) {
-            const float4 f0 = ld4(src + seg * 8);
-            const float4 f1 = ld4(src + seg * 8 + 4);
-            v[j].x = bf16_rne(f0.x) | ((uint32_t)bf16_rne(f0.y) << 16);
-            v[j].y = bf16_rne(f0.z) | ((uint32_t)bf16_rne(f0.w) << 16);
-            v[j].z = bf16_rne(f1.x) | ((uint32_t)bf16_rne(f1.y) << 16);
-            v[j].w = bf16_rne(f1.z) | ((uint32_t)bf16_rne(f1.w) << 16);
-        } else {
-            const float4 f = ld4(src + seg * 4);
-            v[j] = make_uint4(__float_as_uint(f.x), __float_as_uint(f.y), __float_as_uint(f.z), __float_as_uint(f.w));
+        for (int j = 0; j < NC; ++j) {
+            const int cl = 32 * ps + (tid + 256 * j) / (8 * NC);
+            qrow[j] = (int32_t)a.blob[a.qid_word + (cl < m ? cl : 0)];
         }
-    }
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            const int p = tid + 256 * j;
+            const int cl = 32 * ps + p / (8 * NC), seg = p % (8 * NC);
+            const auto src = (cl < m) ? gmem(a.vecs) + (int64_t)qrow[j] * ldv : zero;
+            if constexpr (BF16) {
+                const float4 f0 = ld4(src + seg * 8);
+                const float4 f1 = ld4(src + seg * 8 + 4);
+                v[j].x = bf16_rne(f0.x) | ((uint32_t)bf16_rne(f0.y) << 16);
+                v[j].y = bf16_rne(f0.z) | ((uint32_t)bf16_rne(f0.w) << 16);
+                v[j].z = bf16_rne(f1.x) | ((uint32_t)bf16_rne(f1.y) << 16);
+                v[j].w = bf16_rne(f1.z) | ((uint32_t)bf16_rne(f1.w) << 16);
+            } else {
+                const float4 f = ld4(src + seg * 4);
+                v[j] = make_uint4(__float_as_uint(f.x), __float_as_uint(f.y), __float_as_uint(f.z),
+                                  __float_as_uint(f.w));
+            }
+        }
+    };
+    auto store_cols = [&](void) {
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            const int p = tid + 256 * j;
+            *reinterpret_cast<uint4*>(&Bs[(p / (8 * NC)) * SBB + (p % (8 * NC)) * 16]) = v[j];
+        }
+    };
+    load_cols(0);
     uint4 fa[NC][2];
     {
         const int64_t row = rbase + lr;
@@ -428,124 +471,139 @@ __global__ __launch_bounds__(256) void k_dist_narrow(NarrowArgs a) {
         e_word[r] = (gi < a.U) ? w : -2;
         e_norm[r] = (gi < a.U) ? nv : 0.f;
     }
+    store_cols();
+    int qw[NP][2];
 #pragma unroll
-    for (int j = 0; j < NC; ++j) {
-        const int p = tid + 256 * j;
-        *reinterpret_cast<uint4*>(&Bs[(p / (8 * NC)) * SBB + (p % (8 * NC)) * 16]) = v[j];
-    }
-    int qw[2];
+    for (int ps = 0; ps < NP; ++ps)
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb) {
-        const int k = 16 * nb + lr;
-        qw[nb] = (k < m) ? (int32_t)a.blob[a.qid_word + k] : -1;
-    }
+        for (int nb = 0; nb < 2; ++nb) {
+            const int k = 32 * ps + 16 * nb + lr;
+            qw[ps][nb] = (k < m) ? (int32_t)a.blob[a.qid_word + k] : -1;
+        }
     __syncthreads();
+    if constexpr (NP > 1) load_cols(1);   // in flight during the first pass
 
-    v4f acc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
-    float qn[2] = {0.f, 0.f};
+    v4f acc[NP][2];
+    float qn[NP][2];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        uint4 fb[2][2];
+    for (int ps = 0; ps < NP; ++ps) {
+        if (ps > 0) {
+            __syncthreads();   // every wave is done with the previous columns
+            store_cols();
+            __syncthreads();
+        }
+        acc[ps][0] = acc[ps][1] = v4f{0.f, 0.f, 0.f, 0.f};
+        qn[ps][0] = qn[ps][1] = 0.f;
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb)
+        for (int c = 0; c < NC; ++c) {
+            uint4 fb[2][2];
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
-                fb[nb][h] = *reinterpret_cast<const uint4*>(&Bs[(16 * nb + lr) * SBB + c * 128 + lg * 32 + 16 * h]);
+            for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb)
+                for (int h = 0; h < 2; ++h)
+                    fb[nb][h] = *reinterpret_cast<const uint4*>(&Bs[(16 * nb + lr) * SBB + c * 128 + lg * 32 + 16 * h]);
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const uint32_t w4[4] = {fb[nb][h].x, fb[nb][h].y, fb[nb][h].z, fb[nb][h].w};
+            for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    if constexpr (BF16) {
-                        const float lo = bf16_lo(w4[e]), hi = bf16_hi(w4[e]);
-                        qn[nb] = fmaf(lo, lo, qn[nb]);
-                        qn[nb] = fmaf(hi, hi, qn[nb]);
-                    } else {
-                        const float f = __uint_as_float(w4[e]);
-                        qn[nb] = fmaf(f, f, qn[nb]);
+                for (int h = 0; h < 2; ++h) {
+                    const uint32_t w4[4] = {fb[nb][h].x, fb[nb][h].y, fb[nb][h].z, fb[nb][h].w};
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        if constexpr (BF16) {
+                            const float lo = bf16_lo(w4[e]), hi = bf16_hi(w4[e]);
+                            qn[ps][nb] = fmaf(lo, lo, qn[ps][nb]);
+                            qn[ps][nb] = fmaf(hi, hi, qn[ps][nb]);
+                        } else {
+                            const float f = __uint_as_float(w4[e]);
+                            qn[ps][nb] = fmaf(f, f, qn[ps][nb]);
+                        }
                     }
                 }
-            }
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+            for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int nb = 0; nb < 2; ++nb) {
-                v4f& cc = acc[nb];
-                const uint4 av = fa[c][h], bv = fb[nb][h];
-                if constexpr (BF16) {
-                    cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const v8bf*>(&av),
-                                                                 *reinterpret_cast<const v8bf*>(&bv), cc, 0, 0, 0);
-                } else {
-                    cc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av.x), __uint_as_float(bv.x), cc, 0, 0, 0);
-                    cc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av.y), __uint_as_float(bv.y), cc, 0, 0, 0);
-                    cc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av.z), __uint_as_float(bv.z), cc, 0, 0, 0);
-                    cc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av.w), __uint_as_float(bv.w), cc, 0, 0, 0);
+                for (int nb = 0; nb < 2; ++nb) {
+                    v4f& cc = acc[ps][nb];
+                    const uint4 av = fa[c][h], bv = fb[nb][h];
+                    if constexpr (BF16) {
+                        cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const v8bf*>(&av),
+                                                                     *reinterpret_cast<const v8bf*>(&bv), cc, 0, 0, 0);
+                    } else {
+                        cc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av.x), __uint_as_float(bv.x), cc, 0, 0, 0);
+                        cc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av.y), __uint_as_float(bv.y), cc, 0, 0, 0);
+                        cc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av.z), __uint_as_float(bv.z), cc, 0, 0, 0);
+                        cc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av.w), __uint_as_float(bv.w), cc, 0, 0, 0);
+                    }
                 }
-            }
+        }
     }
 
     // epilogue (the same arithmetic as the general kernel's).  Lane (lr, lg)
-    // holds rows 4 lg + r of columns 16 nb + lr: the wave has every column of
-    // its 16 rows, so the column shift's row minimum is a reduction over the
-    // 16 lanes of a row group, and K is written once (the general kernel needs
-    // atomics and a second pass, as a query's columns span several blocks).
-    float dv[2][4];
-    bool live[2][4];
+    // holds rows 4 lg + r of columns 32 ps + 16 nb + lr: the wave has every
+    // column of its 16 rows, so the column shift's row minimum is a reduction
+    // over the 16 lanes of a row group, and K is written once (the general
+    // kernel needs atomics and a second pass, as a query's columns may span
+    // several blocks).
+    float dv[NP][2][4];
+    bool live[NP][2][4];
+    float dmin[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb) {
-        const float qnj = sum_lane_groups(qn[nb]);
-        const int k = 16 * nb + lr;
+    for (int ps = 0; ps < NP; ++ps)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t gi = rbase + 4 * lg + r;
-            live[nb][r] = k < m && gi < a.U;
-            float d = INFINITY;
-            if (live[nb][r]) {
-                if (e_word[r] == qw[nb]) {
-                    d = 0.f;
-                } else {
-                    float d2 = e_norm[r] + qnj - 2.f * acc[nb][r];
-                    if (d2 < a.tau2) d2 = direct_d2(a.act + gi * ldv, a.vecs + (int64_t)qw[nb] * ldv, ldv);
-                    d = sqrtf(fmaxf(d2, 0.f));
+        for (int nb = 0; nb < 2; ++nb) {
+            const float qnj = sum_lane_groups(qn[ps][nb]);
+            const int k = 32 * ps + 16 * nb + lr;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gi = rbase + 4 * lg + r;
+                live[ps][nb][r] = k < m && gi < a.U;
+                float d = INFINITY;
+                if (live[ps][nb][r]) {
+                    if (e_word[r] == qw[ps][nb]) {
+                        d = 0.f;
+                    } else {
+                        float d2 = e_norm[r] + qnj - 2.f * acc[ps][nb][r];
+                        if (d2 < a.tau2) d2 = direct_d2(a.act + gi * ldv, a.vecs + (int64_t)qw[ps][nb] * ldv, ldv);
+                        d = sqrtf(fmaxf(d2, 0.f));
+                    }
                 }
+                dv[ps][nb][r] = d;
+                dmin[r] = fminf(dmin[r], d);
             }
-            dv[nb][r] = d;
         }
-    }
-    float nmin[4] = {0.f, 0.f, 0.f, 0.f};
     if (a.shift) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            float t = fminf(dv[0][r], dv[1][r]);
+            float t = dmin[r];
 #pragma unroll
             for (int o = 1; o < 16; o <<= 1) t = fminf(t, __shfl_xor(t, o, 64));
-            nmin[r] = t;
+            dmin[r] = t;
             const int64_t gi = rbase + 4 * lg + r;
             if (lr == 0 && gi < a.U) a.nrow[gi] = t;
         }
     }
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb) {
-        const int k = 16 * nb + lr;
-        if (k >= a.ldk) continue;
+    for (int ps = 0; ps < NP; ++ps)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t gi = rbase + 4 * lg + r;
-            if (gi >= a.U) continue;
-            float* kt = a.Kt + gi * a.ldk + k;
-            if (!live[nb][r]) {
-                *kt = 0.f;
-                if (a.km) a.KMt[gi * a.ldk + k] = 0.f;
-                continue;
+        for (int nb = 0; nb < 2; ++nb) {
+            const int k = 32 * ps + 16 * nb + lr;
+            if (k >= a.ldk) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gi = rbase + 4 * lg + r;
+                if (gi >= a.U) continue;
+                float* kt = a.Kt + gi * a.ldk + k;
+                if (!live[ps][nb][r]) {
+                    *kt = 0.f;
+                    if (a.km) a.KMt[gi * a.ldk + k] = 0.f;
+                    continue;
+                }
+                const float d = dv[ps][nb][r];
+                const float kv = a.shift ? expf(-a.lambda * (d - dmin[r])) : expf(-a.lambda * d);
+                *kt = kv;
+                if (a.km) a.KMt[gi * a.ldk + k] = kv * d;
             }
-            const float d = dv[nb][r];
-            const float kv = a.shift ? expf(-a.lambda * (d - nmin[r])) : expf(-a.lambda * d);
-            *kt = kv;
-            if (a.km) a.KMt[gi * a.ldk + k] = kv * d;
         }
-    }
 }
 
 // Log-domain shift, second pass: Kt holds d, nrow holds n_i = min_k d.
@@ -611,9 +669,9 @@ hipError_t launch_dist(const DevCorpus& c, const QueryDev* qd, const int32_t* ko
 }
 
 bool dist_narrow_fits(const DevCorpus& c, int bf16, int B, int ncols, size_t pbytes) {
-    const int nc = c.ldv * (bf16 ? 2 : 4) / 128;
-    return B == 1 && ncols <= 32 && nc >= 1 && nc <= 12 && c.ldv % 64 == 0 && pbytes <= (size_t)kUploadChunkBytes &&
-           pbytes % 4 == 0 && (c.U + TR - 1) / TR <= INT32_MAX;
+    (void)bf16;   // FP32 rows are ldv / 32 chunks of 128 bytes (even), BF16 rows ldv / 64: at most 12 and 6
+    return B == 1 && ncols <= 64 && c.ldv >= 64 && c.ldv <= 384 && c.ldv % 64 == 0 &&
+           pbytes <= (size_t)kUploadChunkBytes && pbytes % 4 == 0 && (c.U + TR - 1) / TR <= INT32_MAX;
 }
 
 hipError_t launch_dist_narrow(const DevCorpus& c, const QueryDev& hq, const void* blob,
@@ -644,15 +702,24 @@ hipError_t launch_dist_narrow(const DevCorpus& c, const QueryDev& hq, const void
     hipError_t e;
     const int nc = c.ldv * (bf16 ? 2 : 4) / 128;
     const unsigned blocks = (unsigned)((c.U + TR - 1) / TR);
-#define WMD_NARROW(K)                                                                        \
-    case K:                                                                                  \
-        e = launch_kernel(bf16 ? k_dist_narrow<true, K> : k_dist_narrow<false, K>, dim3(blocks), \
-                          dim3(256), 0, s, a);                                               \
+    const bool two = hq.ldk > 32;   // a second pass over the next 32 columns
+#define WMD_NARROW(B16, K)                                                                            \
+    case K:                                                                                           \
+        e = launch_kernel(two ? k_dist_narrow<B16, K, 2> : k_dist_narrow<B16, K, 1>, dim3(blocks), dim3(256), \
+                          0, s, a);                                                                   \
         break;
-    switch (nc) {
-        WMD_NARROW(1) WMD_NARROW(2) WMD_NARROW(3) WMD_NARROW(4) WMD_NARROW(5) WMD_NARROW(6)
-        WMD_NARROW(7) WMD_NARROW(8) WMD_NARROW(9) WMD_NARROW(10) WMD_NARROW(11) WMD_NARROW(12)
-        default: return hipErrorInvalidValue;
+    if (bf16) {
+        switch (nc) {
+            WMD_NARROW(true, 1) WMD_NARROW(true, 2) WMD_NARROW(true, 3) WMD_NARROW(true, 4) WMD_NARROW(true, 5)
+            WMD_NARROW(true, 6)
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (nc) {
+            WMD_NARROW(false, 2) WMD_NARROW(false, 4) WMD_NARROW(false, 6) WMD_NARROW(false, 8)
+            WMD_NARROW(false, 10) WMD_NARROW(false, 12)
+            default: return hipErrorInvalidValue;
+        }
     }
 #undef WMD_NARROW
     return e;

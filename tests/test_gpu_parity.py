@@ -168,16 +168,17 @@ def test_batch_equals_single_bitwise(ragged, wmd):
 
 @pytest.mark.parametrize("bf16", [False, True])
 def test_shift_one_query_kernel_equals_batched_bitwise(wmd, bf16):
-    """With the column shift, a short single query runs the one-query distance
-    kernel (row minimum reduced inside the wave, K written once) and a batch
-    the tiled kernel (atomic row minima, then a second pass): the same bits,
-    with K .* M rebuilt from K (lambda 50) and gathered (lambda 0.25)."""
+    """With the column shift, a single query of up to 64 words runs the
+    one-query distance kernel (row minimum reduced inside the wave, K written
+    once; two passes beyond 32 words) and a batch the tiled kernel (row minima
+    by atomics, then a second pass): the same bits, with K .* M rebuilt from K
+    (lambda 50) and gathered (lambda 0.25)."""
     vecs, ptr, ids, w = ragged_corpus(seed=61)
     rng = np.random.default_rng(62)
     with wmd.Corpus(vecs, ptr, ids, w, device=0, bf16=bf16) as c:
         opts = dict(log_domain=True, precision=wmd.WMD_DIST_BF16 if bf16 else wmd.WMD_DIST_FP32)
         queries = [(rng.choice(vecs.shape[0], m, replace=False).astype(np.int32),
-                    rng.geometric(0.5, m).astype(np.float32)) for m in (1, 7, 26, 32)]
+                    rng.geometric(0.5, m).astype(np.float32)) for m in (1, 7, 26, 32, 33, 40, 64)]
         for lam in (50.0, 0.25):
             out, _ = c.query_batch(queries, np.full(len(queries), lam, np.float32),
                                    np.full(len(queries), 12, np.int32), **opts)
