@@ -15,9 +15,9 @@ nothing to overlap, the last Sinkhorn kernel neither) weigh the same in a
 paper-shaped single query (V=100000 words, 300-dim embeddings, N=5000
 documents of 10-60 distinct Zipf(1.1) words, one query of 20-40 words,
 lambda=10, 15 iterations), seeded synthetic data standing in for the paper's
-crawl embeddings and DBpedia documents.  Consecutive queries alternate
-between two streams, so one query's distance GEMM overlaps the previous
-query's Sinkhorn kernel.  Before the K timed steps the queries run for W
+crawl embeddings and DBpedia documents.  Consecutive queries cycle over
+three streams (one per workspace slot of the corpus), so one query's
+distance GEMM overlaps the Sinkhorn kernels of the queries before it.  Before the K timed steps the queries run for W
 steps and at least 0.3 s (the GPU's clocks ramp up under load).
 
 Prints one JSON line: value = documents x iterations / second.  Beside it:
@@ -50,10 +50,9 @@ import time
 import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
-# independent queries in flight on their own streams.  Three (with as many
-# workspace slots) give about 7 % more queries/s on the headline query, but
-# their kernels then queue behind each other's workgroups.
-STREAMS = 2
+# independent queries in flight on their own streams, one per workspace slot
+# of the corpus (three), so no call waits on another stream
+STREAMS = 3
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0            # MI355X HBM3E
@@ -429,7 +428,7 @@ def extensions_section(wmd, corpus, sp, q, qw, calls: int = 200) -> dict:
 def precision_section(wmd, steps: int = 400, sample_docs: int = 400) -> dict:
     """The precision workload: BF16 distances with FP32 accumulation, FP32
     recompute below 1e-2, column-shifted K, lambda = 50, N = 20000; throughput
-    on two streams and per-distance error against the FP64 oracle on sampled
+    on three streams and per-distance error against the FP64 oracle on sampled
     documents (the FP32 path's error beside it)."""
     import torch
     from oracle import sinkhorn_wmd_sparse
@@ -729,9 +728,9 @@ def main():
     info = corpus.info
     N, U, nnz, m, dim = info["N"], info["U"], info["nnz"], q.size, info["dim"]
     h = corpus.handle
-    # consecutive queries alternate between STREAMS streams (and the library's
-    # two workspace slots), so one query's distance GEMM overlaps the previous
-    # query's Sinkhorn kernel
+    # consecutive queries cycle over STREAMS streams (and the library's three
+    # workspace slots), so one query's distance GEMM overlaps the Sinkhorn
+    # kernels of the queries before it
     nstr = max(1, args.headline_streams)
     streams = [torch.cuda.Stream() for _ in range(nstr)]
     outs = [torch.empty(N, dtype=torch.float64, device="cuda") for _ in streams]

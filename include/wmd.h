@@ -181,10 +181,11 @@ int wmd_query(wmd_corpus* corpus, const int32_t* qids, const float* qweights,
  * before return), the outputs are DEVICE pointers to N doubles (dev_resid
  * nullable), written in stream order on `stream`.  The call returns after
  * enqueueing; argument errors are reported synchronously, device faults at
- * the caller's next synchronisation.  A corpus has two workspace slots used in
- * turn: consecutive calls on different streams may run concurrently, and a
+ * the caller's next synchronisation.  A corpus has three workspace slots used
+ * in turn: consecutive calls on different streams may run concurrently, and a
  * call never starts before the call that last used its slot has finished,
- * whatever the streams.  Host-side state is locked, so threads may share a
+ * whatever the streams (calls cycling over three streams keep each slot on
+ * one stream, so no call waits on another stream).  Host-side state is locked, so threads may share a
  * corpus.
  */
 int wmd_query_async(wmd_corpus* corpus, const int32_t* qids, const float* qweights,
@@ -320,13 +321,12 @@ int wmd_timing_get(wmd_corpus* corpus, wmd_timing* out);
  * admitted query holds its own region of the budget (K block, iterate x,
  * results: about 4 (U + N) ldk bytes) until it completes, and at most
  * max_batch queries are in flight.  The worker enqueues steps (at most two
- * ahead): a step runs the distance kernel of the queries admitted into it
- * (on a second stream, beside the previous step), then one Sinkhorn launch
- * per shape class over every in-flight query, each advancing step_iters
- * iterations from its own count (with the final step once it reaches its
- * iteration count), then downloads the results of the queries that
- * finished.  Queries join and leave between steps, so a
- * short query does not wait for a long one to finish.  Results are bitwise
+ * ahead, on one stream): a step runs the distance kernel of the queries
+ * admitted into it, then one Sinkhorn launch per shape class over every
+ * in-flight query, each advancing step_iters iterations from its own count
+ * (with the final step once it reaches its iteration count), then downloads
+ * the results of the queries that finished.  Queries join and leave between
+ * steps, so a short query does not wait for a long one to finish.  Results are bitwise
  * those of wmd_query (the iterate is kept in FP32 between launches, as in a
  * call with iters_per_launch).  Needs tol = 0, lse = 0, iters_per_launch = 0;
  * batch_wait_us and max_inflight are not used.

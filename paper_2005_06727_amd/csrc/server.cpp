@@ -6,10 +6,9 @@
 // every iteration, final step, download) on a stream of its own.  Step mode
 // (step_iters > 0, iteration-level batching): every in-flight query holds its
 // own device region (K block, iterate x, results) across launches, and the
-// worker enqueues steps; a step runs K1 for the queries admitted into it (on
-// a side stream, beside the previous step), then one Sinkhorn launch per
-// shape class over all in-flight
-// queries, each advancing step_iters iterations from its own iteration count
+// worker enqueues steps on one stream; a step runs K1 for the queries
+// admitted into it, then one Sinkhorn launch per shape class over all
+// in-flight queries, each advancing step_iters iterations from its own iteration count
 // (the final step included once its count is reached), then downloads the
 // results of the queries that finished.  Queries join and leave at step
 // boundaries, so a short query admitted next to a long one finishes after
@@ -82,7 +81,6 @@ struct Active {
 
 struct Step {
     hipEvent_t ev = nullptr;
-    hipEvent_t kev = nullptr;          // the step's distance kernel done (side stream)
     std::vector<Active> finishing;     // queries whose results this step downloads
     int queries = 0;                   // queries the step advanced
 };
@@ -90,7 +88,6 @@ struct Step {
 struct StepState {
     static constexpr int kRing = 2;    // steps in flight at most
     hipStream_t stream = nullptr;
-    hipStream_t kstream = nullptr;     // distance kernels of admitted queries, beside the running step
     std::vector<Active> active;        // in-flight queries (worker thread only)
     Step ring[kRing];
     int next = 0;                      // ring entry of the next step
@@ -444,25 +441,20 @@ int enqueue_step(wmd_server* S, int k, std::vector<Active>& act, std::vector<Act
         for (int b = 0; b < A; ++b) hql[fill[act[b].shape + 1]++] = b;
     }
 
-    // The parameter upload and the distance kernel of the admitted queries run
-    // on the side stream, so they overlap the previous step's Sinkhorn
-    // launches; this step's launches wait for them.  (Their regions were free:
-    // memory returns to the pool only when the step that released it retired.)
+    // One stream: a step's distance kernel of the admitted queries, then its
+    // Sinkhorn launches.  (Running the distance kernels on a second stream, to
+    // overlap the previous step, measured no gain: each cross-stream event wait
+    // costs microseconds.)
     const hipStream_t s = st.stream;
-    const hipStream_t sk = nnew > 0 ? st.kstream : s;
     hipError_t e;
-    if ((e = hipMemcpyAsync(dp, hp, pbytes, hipMemcpyHostToDevice, sk)) != hipSuccess)
+    if ((e = hipMemcpyAsync(dp, hp, pbytes, hipMemcpyHostToDevice, s)) != hipSuccess)
         return hip_fail(e, "server: step parameters");
     const QueryDev* dq = reinterpret_cast<const QueryDev*>(dp);
     const int32_t* dql = reinterpret_cast<const int32_t*>(dp + off_ql);
-    if (nnew > 0) {
-        if ((e = launch_dist(dc, dq, reinterpret_cast<const int32_t*>(dp + off_qg), nnew, hqg[nnew],
-                             o.precision == WMD_DIST_BF16 ? 1 : 0, o.log_domain, sk)) != hipSuccess)
-            return hip_fail(e, "server: distance kernel launch");
-        if ((e = hipEventRecord(st.ring[k].kev, sk)) != hipSuccess ||
-            (e = hipStreamWaitEvent(s, st.ring[k].kev, 0)) != hipSuccess)
-            return hip_fail(e, "server: order the step after its distance kernel");
-    }
+    if (nnew > 0 &&
+        (e = launch_dist(dc, dq, reinterpret_cast<const int32_t*>(dp + off_qg), nnew, hqg[nnew],
+                         o.precision == WMD_DIST_BF16 ? 1 : 0, o.log_domain, s)) != hipSuccess)
+        return hip_fail(e, "server: distance kernel launch");
     const int d_tile = (int)c->d_tile;
     auto go = [&](int shape, int q0, int q1, int d0, int d1) -> hipError_t {
         if (q1 <= q0 || d1 <= d0) return hipSuccess;
@@ -567,10 +559,7 @@ void step_worker_main(wmd_server* S) {
                 lk.unlock();
                 std::vector<Active> finishing;
                 const int rc = enqueue_step(S, k, act, finishing);
-                if (rc != WMD_OK) {   // drain what was enqueued
-                    (void)hipStreamSynchronize(st.kstream);
-                    (void)hipStreamSynchronize(st.stream);
-                }
+                if (rc != WMD_OK) (void)hipStreamSynchronize(st.stream);   // drain what was enqueued
                 lk.lock();
                 Step& sp = st.ring[k];
                 if (rc != WMD_OK) {
@@ -608,16 +597,13 @@ void step_worker_main(wmd_server* S) {
 void step_state_free(StepState* st) {
     if (!st) return;
     if (st->stream) (void)hipStreamSynchronize(st->stream);
-    if (st->kstream) (void)hipStreamSynchronize(st->kstream);
     for (int k = 0; k < StepState::kRing; ++k) {
         if (st->ring[k].ev) (void)hipEventDestroy(st->ring[k].ev);
-        if (st->ring[k].kev) (void)hipEventDestroy(st->ring[k].kev);
         if (st->dparams[k]) (void)hipFree(st->dparams[k]);
         if (st->hparams[k]) (void)hipHostFree(st->hparams[k]);
     }
     if (st->h_out) (void)hipHostFree(st->h_out);
     if (st->stream) (void)hipStreamDestroy(st->stream);
-    if (st->kstream) (void)hipStreamDestroy(st->kstream);
     delete st;
 }
 
@@ -625,12 +611,10 @@ int step_state_create(wmd_server* S) {
     StepState* st = new StepState();
     S->steps = st;
     hipError_t e;
-    if ((e = hipStreamCreateWithFlags(&st->stream, hipStreamNonBlocking)) != hipSuccess ||
-        (e = hipStreamCreateWithFlags(&st->kstream, hipStreamNonBlocking)) != hipSuccess)
-        return hip_fail(e, "server: step streams");
+    if ((e = hipStreamCreateWithFlags(&st->stream, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(e, "server: step stream");
     for (int k = 0; k < StepState::kRing; ++k)
-        if ((e = hipEventCreateWithFlags(&st->ring[k].ev, hipEventDisableTiming)) != hipSuccess ||
-            (e = hipEventCreateWithFlags(&st->ring[k].kev, hipEventDisableTiming)) != hipSuccess)
+        if ((e = hipEventCreateWithFlags(&st->ring[k].ev, hipEventDisableTiming)) != hipSuccess)
             return hip_fail(e, "server: step events");
     const size_t per = sizeof(double) * (size_t)S->corpus->dc.N * (S->opt.want_resid ? 2 : 1);
     if ((e = hipHostMalloc(reinterpret_cast<void**>(&st->h_out), per * (size_t)S->opt.max_batch,

@@ -45,7 +45,7 @@ struct Workspace {
     hipStream_t last_stream = nullptr;   // stream of the slot's previous call
     bool carved = false;      // buffers point into memory owned elsewhere (fixed capacity)
 };
-constexpr int kWorkSlots = 2;
+constexpr int kWorkSlots = 3;   // calls cycling over three streams overlap without cross-stream waits
 
 // Sizes and offsets of one call's workspace and parameter block.
 struct Layout {
