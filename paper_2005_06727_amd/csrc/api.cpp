@@ -481,7 +481,8 @@ int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wm
     const int nshape = sinkhorn_num_shapes();
     std::vector<int> cnt(nshape + 1, 0);
     for (int b = 0; b < B; ++b) {
-        if (opt.tile == -2) shape_of[b] = -1;
+        if (opt.lse) shape_of[b] = qs[b].m <= kLseTileMaxM ? 0 : -1;   // log-domain register tile or stream form
+        else if (opt.tile == -2) shape_of[b] = -1;
         else if (opt.tile >= 0) shape_of[b] = opt.tile;
         else shape_of[b] = sinkhorn_shape_for(qs[b].m, kTileMaxDoc, opt.tol > 0.f);
         cnt[shape_of[b] + 1]++;
@@ -534,24 +535,34 @@ int enqueue_queries(wmd_corpus* c, const std::vector<PlannedQuery>& qs, const wm
     }
 
     const int d_tile = (int)c->d_tile;   // sorted docs [d_tile, N) fit the register tiles
-    if (opt.lse) {   // every query and document in one log-domain launch
-        SinkArgs a;
-        a.qd = dq;
-        a.qlist = dql;
-        a.nq = B;
-        a.d_begin = 0;
-        a.d_end = (int)N;
-        a.sptr = dc.sptr;
-        a.scol = dc.scol;
-        a.scw = dc.scw;
-        a.sdoc = dc.sdoc;
-        a.zpad = dc.zpad;
-        a.it_begin = 0;
-        a.it_count = max_iters;
-        a.final_step = 1;
-        if ((e = launch_sinkhorn_lse(a, max_m, dc.max_doc, stream)) != hipSuccess)
+    if (opt.lse) {
+        // queries of at most kLseTileMaxM words against documents that fit the
+        // register tiles: the tile form; everything else: the stream form
+        auto golse = [&](bool tile, int q0, int q1, int d0, int d1) -> hipError_t {
+            if (q1 <= q0 || d1 <= d0) return hipSuccess;
+            SinkArgs a;
+            a.qd = dq;
+            a.qlist = dql + q0;
+            a.nq = q1 - q0;
+            a.d_begin = d0;
+            a.d_end = d1;
+            a.sptr = dc.sptr;
+            a.scol = dc.scol;
+            a.scw = dc.scw;
+            a.sdoc = dc.sdoc;
+            a.zpad = dc.zpad;
+            a.it_begin = 0;
+            a.it_count = max_iters;
+            a.final_step = 1;
+            int mm = 0;
+            for (int i = q0; i < q1; ++i) mm = std::max(mm, qs[hql[i]].m);
+            ++launches;
+            return tile ? launch_sinkhorn_lse_tile(a, stream) : launch_sinkhorn_lse(a, mm, c->h_sorted_len[d0], stream);
+        };
+        if ((e = golse(false, start[0], start[1], 0, (int)N)) != hipSuccess ||
+            (e = golse(false, start[1], B, 0, d_tile)) != hipSuccess ||
+            (e = golse(true, start[1], B, d_tile, (int)N)) != hipSuccess)
             return hip_fail(e, "query: log-domain sinkhorn launch");
-        ++launches;
     }
     for (int it0 = 0; !opt.lse; it0 += per_launch) {
         SinkArgs a;

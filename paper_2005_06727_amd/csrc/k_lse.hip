@@ -323,7 +323,183 @@ __global__ __launch_bounds__(64) void k_sink_lse(SinkArgs g) {
     }
 }
 
+// Register tiles: one wave per (query, document) with the document's whole
+// block of scaled distances L[i][k] = lambda log2(e) d(i, k) in registers
+// (FP64), read from memory once.  Lane (a, b) of the R x C wave holds rows
+// i = a + R p (p < P) and columns k = Q b + q (q < Q); the potentials of its
+// rows (lv) and columns (lu) are kept by every lane that needs them.  A row's
+// log-sum-exp is formed over its Q columns in each lane and combined over
+// the C lanes of the row group (lane bits 0 .. log2 C - 1) with xor
+// shuffles, a column's over its P rows and the R row lanes (the remaining
+// lane bits), so both partners of every step get the same bits and the
+// copies agree.  Rows and columns beyond the block hold a large finite L
+// (their terms underflow to 0 and 0 * L stays 0), and their potentials are
+// kept at 0.  The arithmetic is the stream kernel's: FP64 exponent
+// arguments and maxima, FP32 2^(a - max) and sums; log2 of the sums in FP32
+// (an error below 4e-7 in a potential).
+constexpr double kPadL = 1e300;
+
+template <int G, typename T>
+__device__ __forceinline__ T xmax(T v, int lo) {
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) v = fmax(v, __shfl_xor(v, o * lo, 64));
+    return v;
+}
+template <int G, typename T>
+__device__ __forceinline__ T xsum(T v, int lo) {
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o * lo, 64);
+    return v;
+}
+
+// One document with PN rows per lane (PN = ceil(n / R), chosen per wave: a
+// wave holds one document, so rows beyond it cost nothing).
+template <int R, int C, int PN, int Q>
+__device__ __forceinline__ void lse_tile_doc(const SinkArgs& g, const QueryDev* qp, const int d, const int rs,
+                                             const int n, const int lane) {
+    const int a = lane / C, b = lane % C;
+    const int m = qp->m, ldk = qp->ldk;
+    const double lam2 = (double)qp->lambda * kLog2e;
+    const auto D = gmem(reinterpret_cast<const double*>(qp->Kt));
+    const int kb = Q * b;
+
+    double L[PN][Q];
+    double lv[PN], lc[PN];
+    float cw[PN];
+    bool rv[PN];
+#pragma unroll
+    for (int p = 0; p < PN; ++p) {
+        const int i = a + R * p;
+        rv[p] = i < n;
+        const int e = rs + (rv[p] ? i : 0);
+        const int col = g.scol[e];
+        cw[p] = rv[p] ? g.scw[e] : 0.f;
+        const auto row = D + (int64_t)col * ldk;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int k = kb + q;
+            const double dv = row[k < m ? k : 0];
+            L[p][q] = (rv[p] && k < m) ? lam2 * dv : kPadL;
+        }
+    }
+    const auto rq = gmem(qp->r);
+    double lu[Q], lr[Q];
+    bool cv[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int k = kb + q;
+        cv[q] = k < m;
+        const float r = rq[cv[q] ? k : 0];
+        lr[q] = cv[q] ? log2((double)r) : 0.0;
+        lu[q] = cv[q] ? log2((double)m) : 0.0;   // x = 1/v_r, u = 1/x
+    }
+#pragma unroll
+    for (int p = 0; p < PN; ++p) {
+        lc[p] = rv[p] ? log2((double)cw[p]) : 0.0;
+        lv[p] = 0.0;
+    }
+
+    // rows: lv_i = log2 c_i - LSE2_k(lu_k - L_ik); final: c_i (sum_k w_ik d_ik) / (sum_k w_ik)
+    auto rows = [&](bool final) -> double {
+        double wsum = 0.0;
+#pragma unroll
+        for (int p = 0; p < PN; ++p) {
+            double mx = -INFINITY;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) mx = fmax(mx, lu[q] - L[p][q]);
+            mx = xmax<C>(mx, 1);
+            float sv = 0.f;
+            double sd = 0.0;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const float w = __builtin_amdgcn_exp2f((float)((lu[q] - L[p][q]) - mx));
+                sv += w;
+                if (final) sd = fma((double)w, L[p][q], sd);
+            }
+            sv = xsum<C>(sv, 1);
+            if (final) {
+                sd = xsum<C>(sd, 1);
+                if (rv[p] && b == 0) wsum += (double)cw[p] * (sd / lam2) / (double)sv;
+            } else {
+                lv[p] = rv[p] ? lc[p] - (mx + (double)__log2f(sv)) : 0.0;
+            }
+        }
+        return wsum;
+    };
+    // columns: lu_k = log2 r_k - LSE2_i(lv_i - L_ik); with resid,
+    // sum_k |P1_k - r_k| where P1_k = 2^(lu_k + LSE2_i(...))
+    auto cols = [&](bool resid) -> double {
+        double rsum = 0.0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            double mx = -INFINITY;
+#pragma unroll
+            for (int p = 0; p < PN; ++p) mx = fmax(mx, lv[p] - L[p][q]);
+            mx = xmax<R>(mx, C);
+            float sv = 0.f;
+#pragma unroll
+            for (int p = 0; p < PN; ++p) sv += __builtin_amdgcn_exp2f((float)((lv[p] - L[p][q]) - mx));
+            sv = xsum<R>(sv, C);
+            const double l = mx + (double)__log2f(sv);
+            if (resid) {
+                if (cv[q] && a == 0) rsum += fabs(exp2(lu[q] + l) - (double)rq[kb + q]);
+            } else {
+                lu[q] = cv[q] ? lr[q] - l : 0.0;
+            }
+        }
+        return rsum;
+    };
+
+    for (int it = 0; it < qp->iters; ++it) {
+        rows(false);
+        cols(false);
+    }
+    if (qp->resid) rows(false);   // the final v, for the residual's column sums
+    double wsum = rows(true);
+    double rsum = qp->resid ? cols(true) : 0.0;
+    wsum = xsum<64>(wsum, 1);
+    rsum = xsum<64>(rsum, 1);
+    if (lane == 0) {
+        const int doc = g.sdoc[d];
+        gmem(qp->out)[doc] = wsum;
+        if (qp->resid) gmem(qp->resid)[doc] = rsum;
+        if (qp->it_out) gmem(qp->it_out)[doc] = qp->iters;
+    }
+}
+
+template <int R, int C, int P, int Q, int PN>
+__device__ __forceinline__ void lse_tile_dispatch(int pr, const SinkArgs& g, const QueryDev* qp, int d, int rs,
+                                                  int n, int lane) {
+    if constexpr (PN >= P) {
+        lse_tile_doc<R, C, P, Q>(g, qp, d, rs, n, lane);
+    } else {
+        if (pr <= PN) lse_tile_doc<R, C, PN, Q>(g, qp, d, rs, n, lane);
+        else lse_tile_dispatch<R, C, P, Q, PN + 1>(pr, g, qp, d, rs, n, lane);
+    }
+}
+
+template <int R, int C, int P, int Q>
+__global__ __launch_bounds__(64) void k_sink_lse_tile(SinkArgs g) {
+    static_assert(R * C == 64, "one wave per document");
+    const int lane = threadIdx.x;
+    const int64_t item = blockIdx.x;
+    const int nd = g.d_end - g.d_begin;
+    const int qidx = g.single ? 0 : g.qlist[item / nd];
+    const int d = g.d_begin + (int)(item % nd);
+    const QueryDev* qp = g.qd + qidx;
+    const int rs = g.sptr[d], n = g.sptr[d + 1] - rs;
+    // the wave's document is uniform: rows per lane as an SGPR
+    const int pr = __builtin_amdgcn_readfirstlane((n + R - 1) / R);
+    lse_tile_dispatch<R, C, P, Q, 1>(pr, g, qp, d, rs, n, lane);
+}
+
 }  // namespace
+
+hipError_t launch_sinkhorn_lse_tile(const SinkArgs& a, hipStream_t s) {
+    const int64_t nitems = (int64_t)a.nq * (a.d_end - a.d_begin);
+    if (nitems <= 0) return hipSuccess;
+    return launch_kernel(k_sink_lse_tile<8, 8, 8, 5>, dim3((unsigned)nitems), dim3(64), 0, s, a);
+}
 
 size_t lse_dist_lds_bytes(int ldv) { return sizeof(float) * (size_t)kCols * (ldv + 4); }
 

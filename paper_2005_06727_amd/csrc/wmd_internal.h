@@ -108,6 +108,10 @@ size_t lse_sink_lds_bytes(int max_m, int max_n);
 hipError_t launch_dist_lse(const DevCorpus& c, const QueryDev* qd, const int32_t* kofs, int B, int ncols,
                            hipStream_t s);
 hipError_t launch_sinkhorn_lse(const SinkArgs& a, int max_m, int max_n, hipStream_t s);
+// Its register-tile form: queries of at most kLseTileMaxM words against
+// documents of at most kTileMaxDoc (64) words, the distance block in registers.
+constexpr int kLseTileMaxM = 40;
+hipError_t launch_sinkhorn_lse_tile(const SinkArgs& a, hipStream_t s);
 hipError_t launch_prep_norms(const float* rows, int64_t nrows, int ldv, float* norms, hipStream_t s);
 hipError_t launch_prep_bf16(const float* src, uint16_t* dst, float* norms, int64_t nrows, int ldv,
                             hipStream_t s);
