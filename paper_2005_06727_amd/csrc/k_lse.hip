@@ -339,17 +339,68 @@ __global__ __launch_bounds__(64) void k_sink_lse(SinkArgs g) {
 // (an error below 4e-7 in a potential).
 constexpr double kPadL = 1e300;
 
-template <int G, typename T>
-__device__ __forceinline__ T xmax(T v, int lo) {
-#pragma unroll
-    for (int o = 1; o < G; o <<= 1) v = fmax(v, __shfl_xor(v, o * lo, 64));
-    return v;
+// One butterfly step over lane bit log2(O): each lane combines its value with
+// that of lane ^ O (DPP moves within a 16-lane row for O <= 8, the gfx950
+// permlane swaps for 16 and 32), so both partners get the same bits.
+template <int O>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v) {
+    static_assert(O == 1 || O == 2 || O == 4 || O == 8, "DPP offsets");
+    const int i = (int)v;
+    if constexpr (O == 1) return (uint32_t)__builtin_amdgcn_update_dpp(i, i, 0xB1, 0xF, 0xF, false);
+    else if constexpr (O == 2) return (uint32_t)__builtin_amdgcn_update_dpp(i, i, 0x4E, 0xF, 0xF, false);
+    else if constexpr (O == 8) return (uint32_t)__builtin_amdgcn_update_dpp(i, i, 0x128, 0xF, 0xF, false);
+    else {
+        // banks 0 and 2 (lanes 0-3, 8-11 of a row) read lane + 4, banks 1 and 3 lane - 4
+        int t = __builtin_amdgcn_update_dpp(i, i, 0x104, 0xF, 0x5, false);
+        t = __builtin_amdgcn_update_dpp(t, i, 0x114, 0xF, 0xA, false);
+        return (uint32_t)t;
+    }
 }
-template <int G, typename T>
-__device__ __forceinline__ T xsum(T v, int lo) {
-#pragma unroll
-    for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o * lo, 64);
-    return v;
+
+template <int O, bool MAX>
+__device__ __forceinline__ double xstep(double v) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)u, hi = (uint32_t)(u >> 32);
+    double x, y;
+    if constexpr (O <= 8) {
+        x = v;
+        y = __longlong_as_double((long long)(((uint64_t)xor_lane<O>(hi) << 32) | xor_lane<O>(lo)));
+    } else {
+        auto rl = (O == 16) ? __builtin_amdgcn_permlane16_swap(lo, lo, false, false)
+                            : __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        auto rh = (O == 16) ? __builtin_amdgcn_permlane16_swap(hi, hi, false, false)
+                            : __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        x = __longlong_as_double((long long)(((uint64_t)rh[0] << 32) | rl[0]));
+        y = __longlong_as_double((long long)(((uint64_t)rh[1] << 32) | rl[1]));
+    }
+    return MAX ? fmax(x, y) : x + y;
+}
+
+template <int O, bool MAX>
+__device__ __forceinline__ float xstep(float v) {
+    const uint32_t u = __float_as_uint(v);
+    float x, y;
+    if constexpr (O <= 8) {
+        x = v;
+        y = __uint_as_float(xor_lane<O>(u));
+    } else {
+        auto r = (O == 16) ? __builtin_amdgcn_permlane16_swap(u, u, false, false)
+                           : __builtin_amdgcn_permlane32_swap(u, u, false, false);
+        x = __uint_as_float(r[0]);
+        y = __uint_as_float(r[1]);
+    }
+    return MAX ? fmaxf(x, y) : x + y;
+}
+
+// all-reduce over the G lanes at stride LO (lane bits log2 LO .. log2 LO G - 1)
+template <int G, int LO, bool MAX, typename T>
+__device__ __forceinline__ T xred(T v) {
+    if constexpr (G > 1) {
+        v = xstep<LO, MAX>(v);
+        return xred<G / 2, LO * 2, MAX>(v);
+    } else {
+        return v;
+    }
 }
 
 // One document with PN rows per lane (PN = ceil(n / R), chosen per wave: a
@@ -407,7 +458,7 @@ __device__ __forceinline__ void lse_tile_doc(const SinkArgs& g, const QueryDev* 
             double mx = -INFINITY;
 #pragma unroll
             for (int q = 0; q < Q; ++q) mx = fmax(mx, lu[q] - L[p][q]);
-            mx = xmax<C>(mx, 1);
+            mx = xred<C, 1, true>(mx);
             float sv = 0.f;
             double sd = 0.0;
 #pragma unroll
@@ -416,9 +467,9 @@ __device__ __forceinline__ void lse_tile_doc(const SinkArgs& g, const QueryDev* 
                 sv += w;
                 if (final) sd = fma((double)w, L[p][q], sd);
             }
-            sv = xsum<C>(sv, 1);
+            sv = xred<C, 1, false>(sv);
             if (final) {
-                sd = xsum<C>(sd, 1);
+                sd = xred<C, 1, false>(sd);
                 if (rv[p] && b == 0) wsum += (double)cw[p] * (sd / lam2) / (double)sv;
             } else {
                 lv[p] = rv[p] ? lc[p] - (mx + (double)__log2f(sv)) : 0.0;
@@ -435,11 +486,11 @@ __device__ __forceinline__ void lse_tile_doc(const SinkArgs& g, const QueryDev* 
             double mx = -INFINITY;
 #pragma unroll
             for (int p = 0; p < PN; ++p) mx = fmax(mx, lv[p] - L[p][q]);
-            mx = xmax<R>(mx, C);
+            mx = xred<R, C, true>(mx);
             float sv = 0.f;
 #pragma unroll
             for (int p = 0; p < PN; ++p) sv += __builtin_amdgcn_exp2f((float)((lv[p] - L[p][q]) - mx));
-            sv = xsum<R>(sv, C);
+            sv = xred<R, C, false>(sv);
             const double l = mx + (double)__log2f(sv);
             if (resid) {
                 if (cv[q] && a == 0) rsum += fabs(exp2(lu[q] + l) - (double)rq[kb + q]);
@@ -457,8 +508,8 @@ __device__ __forceinline__ void lse_tile_doc(const SinkArgs& g, const QueryDev* 
     if (qp->resid) rows(false);   // the final v, for the residual's column sums
     double wsum = rows(true);
     double rsum = qp->resid ? cols(true) : 0.0;
-    wsum = xsum<64>(wsum, 1);
-    rsum = xsum<64>(rsum, 1);
+    wsum = xred<64, 1, false>(wsum);
+    rsum = xred<64, 1, false>(rsum);
     if (lane == 0) {
         const int doc = g.sdoc[d];
         gmem(qp->out)[doc] = wsum;
