@@ -95,7 +95,7 @@ typedef struct wmd_query_options {
                                  FP32 accuracy bar holds at any lambda.  Needs precision
                                  WMD_DIST_FP32, tol = 0, iters_per_launch = 0, tile = -1
                                  and log_domain = 0 (WMD_EINVAL otherwise).  Limits:
-                                 8 * (embedding row + 4) floats (the distance kernel's
+                                 32 * (embedding row + 4) floats (the distance kernel's
                                  staged query rows) and 16 (v_r + longest document) +
                                  4 (longest document + 1) bytes (the iteration's
                                  vectors) of LDS, each at most 160 KB (WMD_EINVAL
