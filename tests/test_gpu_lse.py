@@ -41,7 +41,7 @@ def _query(V, m, seed):
 
 
 @pytest.mark.parametrize("lam", [10.0, 300.0, 3000.0])
-@pytest.mark.parametrize("m", [1, 6, 26, 70, 300])
+@pytest.mark.parametrize("m", [1, 6, 26, 40, 41, 70, 300])   # 40 / 41: the register tile's bound
 def test_lse_matches_log_domain_oracle(ragged, m, lam):
     (vecs, ptr, ids, w), c = ragged
     q, qw = _query(vecs.shape[0], m, m)
