@@ -813,6 +813,7 @@ def main():
     sink_flops_exec = 2.0 * nnz * m * (2 * t_it + 1) + 2.0 * nnz * m
     # compulsory bytes: K block of the corpus words (once), CSR, results
     sink_bytes = 4.0 * U * m + 8.0 * nnz + 8.0 * (N + 1) + 8.0 * N
+    it_bytes = 4.0 * m * U + 8.0 * nnz + 4.0 * (N + 1) + 8.0 * m * N
     dist_bytes = 4.0 * U * dim + 4.0 * m * dim + 4.0 * U * m
     dist_flops = 2.0 * U * dim * m
     tcalls = max(tim["calls"], 1)
@@ -824,7 +825,12 @@ def main():
             "frac": sink_flops / sink_s / 1e12 / PEAK_FP32_TFLOPS,
             "frac_of_unpacked_fp32_issue_rate": sink_flops / sink_s / 1e12 / PEAK_FP32_UNPACKED_TFLOPS,
             "algorithmic_flops": sink_flops, "flops_as_executed": sink_flops_exec,
-            "compulsory_bytes": sink_bytes, "compulsory_GBps": sink_bytes / sink_s / 1e9},
+            "compulsory_bytes": sink_bytes, "compulsory_GBps": sink_bytes / sink_s / 1e9,
+            # the per-iteration form's bound: it would move B_it = 4 v_r U + 8 nnz + 4 (N + 1)
+            # + 8 v_r N bytes in every iteration; t of them in the fused kernel's time
+            "per_iteration_form_equivalent": {
+                "bytes_per_iteration": it_bytes, "GBps": it_bytes * t_it / sink_s / 1e9,
+                "frac_of_hbm_peak": it_bytes * t_it / sink_s / 1e9 / PEAK_HBM_GBS}},
         "dist_gemm": {
             "avg_us": dist_s * 1e6, "avg_us_in_pipeline": in_pipeline(tim["dist_ms"]),
             "bound": "hbm", "achieved": dist_bytes / dist_s / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
