@@ -310,10 +310,17 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
     constexpr int LC = ilog2(C), LR = ilog2(R), LQ = ilog2(Q);
     constexpr int RSB = (LR < LQ) ? LR : LQ;
     constexpr int ARB = LR - RSB;
-    constexpr int F = Q >> RSB;
-    static_assert((1 << LC) == C && (1 << LR) == R && (1 << LQ) == Q && C >= 4, "team shape");
+    constexpr bool XLDS0 = (ARB == 0) && (C < 16);
+    // Q need not be a power of two when the sums go through LDS: the R row
+    // lanes then own ceil(Q / R) columns each, the last lanes fewer or none
+    constexpr int F = XLDS0 ? (Q + R - 1) / R : Q >> RSB;
+    constexpr bool EXACT = F * R == Q || !XLDS0;
+    static_assert((1 << LC) == C && (1 << LR) == R && C >= 4, "team shape");
+    static_assert((1 << LQ) == Q || XLDS0, "Q is a power of two unless the sums go through LDS");
     const int kf = kb + (a >> ARB) * F;              // first owned column
     const bool lead = (a & ((1 << ARB) - 1)) == 0;
+    // owned column f lies in this lane's column group (always, unless Q is not R F)
+    auto owned = [&](int f) -> bool { return EXACT || (a >> ARB) * F + f < Q; };
     // Teams with at least as many columns as row lanes, whose row lanes sit
     // on the low lane bits (C < 16, where the shuffles need DPP bank moves,
     // selects and wait states; the permlane swaps of bits 4 and 5 are cheaper
@@ -323,7 +330,7 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
     // u of its columns back.  s_x is this wave's region (each wave of a team
     // has its own C Q columns): R x XS partials, then C Q values of u,
     // indexed by the column within the wave (kbl, kfl).
-    constexpr bool XLDS = (ARB == 0) && (C < 16);
+    constexpr bool XLDS = XLDS0;
     constexpr int XS = C * Q + 4;                    // partial-sum row stride (floats)
     float* const s_u = s_x + R * XS;
     const int kbl = b * Q, kfl = kbl + (a >> ARB) * F;
@@ -416,7 +423,7 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
 #pragma unroll
     for (int f = 0; f < F; ++f) {
         const int k = kf + f;
-        const bool kv = k < m;
+        const bool kv = k < m && owned(f);
         const int kc = kv ? k : 0;
         const float ri = rinvp[kc];
         const float rv = rp[kc];
@@ -428,7 +435,7 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
         const auto xp = gmem(qp->x) + (int64_t)d * ldk;
 #pragma unroll
         for (int f = 0; f < F; ++f) {
-            const bool kv = kf + f < m;
+            const bool kv = kf + f < m && owned(f);
             const float xv = xp[kv ? kf + f : 0];
             x[f] = kv ? xv : 1.f;
         }
@@ -441,7 +448,7 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
 #pragma unroll
             for (int f = 0; f < F; ++f) {
                 uo[f] = rcp(x[f]);
-                s_u[kfl + f] = uo[f];
+                if (owned(f)) s_u[kfl + f] = uo[f];
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -588,7 +595,7 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
         if (valid && lead) {
 #pragma unroll
             for (int f = 0; f < F; ++f)
-                if (kf + f < m) gmem(qp->x)[(int64_t)d * ldk + kf + f] = x[f];
+                if (kf + f < m && owned(f)) gmem(qp->x)[(int64_t)d * ldk + kf + f] = x[f];
         }
         return;
     }
@@ -604,7 +611,7 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
         if (want_resid && lead) {
 #pragma unroll
             for (int f = 0; f < F; ++f)
-                if (kf + f < m) rho += fabs((double)uo[f] * (double)y[f] - (double)gmem(qp->r)[kf + f]);
+                if (kf + f < m && owned(f)) rho += fabs((double)uo[f] * (double)y[f] - (double)gmem(qp->r)[kf + f]);
         }
     }
 
@@ -694,9 +701,10 @@ __device__ __forceinline__ void sink_dispatch(const int pr, Args&&... args) {
 }
 
 // Occupancy targets: 5 waves per SIMD for 4 rows per lane, 3 for 8, 2 for
-// 16; the multi-wave teams take what their registers allow.
+// 16 rows or more than 8 columns per lane; the multi-wave teams take what
+// their registers allow.
 template <int R, int C, int P, int Q, int W>
-__global__ __launch_bounds__(256, (W > 1) ? 1 : (P >= 16) ? 2 : (P <= 4) ? 5 : 3) void k_sink(SinkArgs g) {
+__global__ __launch_bounds__(256, (W > 1) ? 1 : (P >= 16 || Q > 8) ? 2 : (P <= 4) ? 5 : 3) void k_sink(SinkArgs g) {
     constexpr int T = R * C;
     static_assert(W == 1 || T == 64, "multi-wave teams use whole waves");
     static_assert(Q % 4 == 0, "columns are loaded as float4");
@@ -1084,11 +1092,12 @@ const Shape kShapes[] = {
     make_rows_shape<32, 1>(),        // 9: m <= 32,  row lanes
     make_rows_shape<64, 1>(),        // 10: m <= 64, row lanes
     make_shape<16, 4, 4, 8, 1>(),    // 11: m <= 32,  one wave per document
+    make_shape<8, 4, 8, 12, 1>(),    // 12: m <= 48,  32-lane teams, 12 columns per lane
 };
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 // default shape per query-length class (first entry whose max_m covers m)
-const int kDefaultShapes[] = {8, 2, 3, 5, 6, 7};   // chosen by measurement on the c2-shaped corpus
-const int kAdaptiveShapes[] = {0, 2, 3, 5, 6, 7};  // register tiles only (convergence check)
+const int kDefaultShapes[] = {8, 2, 12, 3, 5, 6, 7};   // chosen by measurement on the c2-shaped corpus
+const int kAdaptiveShapes[] = {0, 2, 12, 3, 5, 6, 7};  // register tiles only (convergence check)
 
 }  // namespace
 
