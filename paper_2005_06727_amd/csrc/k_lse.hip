@@ -56,7 +56,8 @@ __device__ int query_of_col(const int32_t* kofs, int B, int c) {
 // columns, whose query rows are staged in LDS (FP32, row stride ldv + 4) and
 // read as broadcasts.  Columns m_b <= k < ldk_b are written as zeros.  32
 // columns per block (one whole query of up to 32 words) read each corpus row
-// once per query where 8 read it four times (c4: 4.8e8 -> 6.3e8 doc*iters/s).
+// once per query where 8 read it four times (20000 documents of 10-60 words,
+// lambda 1000: 4.8e8 -> 6.3e8 doc*iters/s).
 __global__ __launch_bounds__(kRows) void k_dist_lse(LseDistArgs a) {
     extern __shared__ float4 qsh4[];
     float* qsh = reinterpret_cast<float*>(qsh4);
