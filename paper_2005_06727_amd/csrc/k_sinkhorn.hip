@@ -296,7 +296,7 @@ template <int R, int C, int P, int Q, int W, int PN>
 __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp, const bool valid, const int d,
                                           const int rs, const int n, const int m, const int ldk, const int a,
                                           const int b, const int tl, const int wi, const int team, const int kb,
-                                          const int it_end, const int my_end, float* s_part, double* s_red,
+                                          const int it_end, float* s_part, double* s_red,
                                           float* s_rho, float* s_x) {
     constexpr int T = R * C;
     constexpr int Q4 = Q / 4;
@@ -556,13 +556,9 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
         sddmm();
         spmm();
         if (!adaptive) {
-            // teams of a multi-wave block run the block's largest iteration count
-            // (same barriers); a team past its own count computes but keeps x
-            if (W == 1 || it < my_end) {
 #pragma unroll
-                for (int f = 0; f < F; ++f) x[f] = fmaf(y[f], rinv[f], kXPad);
-                t_done = it + 1;
-            }
+            for (int f = 0; f < F; ++f) x[f] = fmaf(y[f], rinv[f], kXPad);
+            t_done = it + 1;
         } else {
             // rho = sum_k r_k |x_new / x_old - 1|, with u = 1 / x_old from above,
             // over the owned columns, then over the whole team
@@ -581,7 +577,7 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
                 rho = 0.f;
                 for (int w2 = 0; w2 < W; ++w2) rho += s_rho[team * W + w2];
             }
-            if (!done && (W == 1 || it < my_end)) {
+            if (!done) {
 #pragma unroll
                 for (int f = 0; f < F; ++f) x[f] = xn[f];
                 t_done = it + 1;
@@ -715,7 +711,6 @@ __global__ __launch_bounds__(256, (W > 1) ? 1 : (P >= 16 || Q > 8) ? 2 : (P <= 4
 
     __shared__ float s_part[(W > 1) ? TEAMS * 2 * W * R * P : 1];
     __shared__ double s_red[(W > 1) ? TEAMS * W * 2 : 1];
-    __shared__ int s_itmax[(W > 1) ? TEAMS : 1];
     __shared__ float s_rho[(W > 1) ? TEAMS * W : 1];
     // per-team exchange region of the one-wave tiles (see sink_team)
     constexpr bool XL = (R <= Q) && (C < 16);
@@ -749,19 +744,10 @@ __global__ __launch_bounds__(256, (W > 1) ? 1 : (P >= 16 || Q > 8) ? 2 : (P <= 4
     const int n = valid ? re - rs : 0;
     const int kb = (wi * C + b) * Q;
 
-    int it_end = valid ? min(g.it_begin + g.it_count, qp->iters) : g.it_begin;
-    if constexpr (W > 1) {
-        // every wave of the block must run the same number of barriers
-        if (tid < TEAMS) s_itmax[tid] = g.it_begin;
-        __syncthreads();
-        if (tl == 0 && wi == 0) atomicMax(&s_itmax[team], it_end);
-        __syncthreads();
-        int mx = g.it_begin;
-        for (int t2 = 0; t2 < TEAMS; ++t2) mx = max(mx, s_itmax[t2]);
-        __syncthreads();
-        it_end = mx;
-    }
-    const int my_end = valid ? min(g.it_begin + g.it_count, qp->iters) : g.it_begin;
+    // Every team of a multi-wave block runs the query's iteration count (the
+    // query is uniform over the block), a padding team too, so all waves run
+    // the same barriers; a padding team stores nothing.
+    const int it_end = (valid || W > 1) ? min(g.it_begin + g.it_count, qp->iters) : g.it_begin;
 
     // rows per lane for this wave: the most any of its teams needs (documents
     // of a launch are sorted by length, so the teams of a wave have similar n).
@@ -773,7 +759,7 @@ __global__ __launch_bounds__(256, (W > 1) ? 1 : (P >= 16 || Q > 8) ? 2 : (P <= 4
         for (int t = 1; t < TPW; ++t) pr = max(pr, __builtin_amdgcn_readlane(nrl, t * T));
     }
     sink_dispatch<R, C, P, Q, W, (P >= 16) ? 2 : 1, (P >= 16) ? 2 : 1>(
-        pr, g, qp, valid, d, rs, n, m, ldk, a, b, tl, wi, team, kb, it_end, my_end, s_part, s_red, s_rho,
+        pr, g, qp, valid, d, rs, n, m, ldk, a, b, tl, wi, team, kb, it_end, s_part, s_red, s_rho,
         s_x + (XL ? (team * W + wi) * XTEAM : 0));
 }
 
@@ -1066,17 +1052,19 @@ __global__ __launch_bounds__(64) void k_sink_rows(SinkArgs g) {
 
 struct Shape {
     int max_m, max_n, teams_per_block, threads;
+    bool tile;   // a register tile (implements the convergence check)
     void (*kern)(SinkArgs);
 };
 
 template <int R, int C, int P, int Q, int W>
 constexpr Shape make_shape() {
-    return Shape{C * Q * W, R * P, (W == 1) ? 4 * (64 / (R * C)) : 4 / W, 256, &k_sink<R, C, P, Q, W>};
+    return Shape{C * Q * W, R * P, (W == 1) ? 4 * (64 / (R * C)) : 4 / W, 256, true,
+                 &k_sink<R, C, P, Q, W>};
 }
 
 template <int MQ, int RP>
 constexpr Shape make_rows_shape() {
-    return Shape{MQ, 64 * RP, 1, 64, &k_sink_rows<MQ, RP>};
+    return Shape{MQ, 64 * RP, 1, 64, false, &k_sink_rows<MQ, RP>};
 }
 
 const Shape kShapes[] = {
@@ -1109,7 +1097,7 @@ const int kAdaptiveShapes[] = {0, 2, 12, 3, 13, 5, 14, 6, 15, 7};  // register t
 
 int sinkhorn_num_shapes() { return kNumShapes; }
 
-bool sinkhorn_shape_adaptive(int shape) { return shape < 0 || kShapes[shape].threads == 256; }
+bool sinkhorn_shape_adaptive(int shape) { return shape < 0 || kShapes[shape].tile; }
 
 int sinkhorn_shape_for(int m, int max_n, bool adaptive) {
     for (int s : (adaptive ? kAdaptiveShapes : kDefaultShapes))
