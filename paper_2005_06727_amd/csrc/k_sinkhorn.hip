@@ -33,6 +33,8 @@
 // relative error stays at FP32 rounding level.  Optionally the FP64 residual
 // sum_k |u_k (A^T v)_k - r_k| of the plan's row marginal (its column marginal
 // is c by construction).
+#include <atomic>
+
 #include "wmd_device.h"
 #include "launch.h"
 #include "wmd_internal.h"
@@ -407,11 +409,10 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
             }
         }
     }
-    // the act row index of row p (valid rows only)
-    auto col_of = [&](int p) -> int {
-        if constexpr (W == 1) return col[p];
-        else return g.scol[rs + a + R * p];
-    };
+    // the act row index of row p (valid rows only), read again where needed
+    // (the final step, with the column shift or K .* M gathered) rather than
+    // held in registers through the iterations
+    auto col_of = [&](int p) -> int { return g.scol[rs + a + R * p]; };
 
     // per-column vectors, also branch-free; a column beyond m reads element 0
     const auto rinvp = gmem(qp->rinv);
@@ -684,6 +685,22 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
     }
 }
 
+// Occupancy targets (waves per SIMD) of the one-wave register tiles: 5 for 4
+// rows per lane, 3 for 8 rows of up to 12 columns (12 columns spill a few
+// registers of the load phase to reach it, still faster than 2 waves), 2 for
+// 16 rows or 16 columns.  The multi-wave teams take what their registers allow
+// (the 12-column ones reach 3).  `dense`: a second build of the 8 x 8 tiles at
+// 4 waves (spilling a few registers), faster when the launch has more waves
+// than 3 per SIMD, slower for a single query on a small corpus.
+template <int P, int Q, int W, bool dense>
+constexpr int sink_occupancy() {
+    if constexpr (W > 1) return 1;
+    else if constexpr (P >= 16 || Q > 12) return 2;
+    else if constexpr (P <= 4) return 5;
+    else if constexpr (dense && Q <= 8) return 4;
+    else return 3;
+}
+
 // The smallest compiled PN (a multiple of STEP, at most P) that covers pr
 // rows per lane.  Results do not depend on PN: padded rows add exact zeros.
 template <int R, int C, int P, int Q, int W, int PN, int STEP, typename... Args>
@@ -696,11 +713,9 @@ __device__ __forceinline__ void sink_dispatch(const int pr, Args&&... args) {
     }
 }
 
-// Occupancy targets: 5 waves per SIMD for 4 rows per lane, 3 for 8, 2 for
-// 16 rows or more than 8 columns per lane; the multi-wave teams take what
-// their registers allow.
-template <int R, int C, int P, int Q, int W>
-__global__ __launch_bounds__(256, (W > 1) ? 1 : (P >= 16 || Q > 8) ? 2 : (P <= 4) ? 5 : 3) void k_sink(SinkArgs g) {
+// Occupancy target OCC (waves per SIMD), see sink_occupancy.
+template <int R, int C, int P, int Q, int W, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_sink(SinkArgs g) {
     constexpr int T = R * C;
     static_assert(W == 1 || T == 64, "multi-wave teams use whole waves");
     static_assert(Q % 4 == 0, "columns are loaded as float4");
@@ -1050,21 +1065,38 @@ __global__ __launch_bounds__(64) void k_sink_rows(SinkArgs g) {
     }
 }
 
+// Compute units of the current device (cached per device).
+int device_cus() {
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    int n = cache[dev].load(std::memory_order_relaxed);
+    if (n == 0) {
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cache[dev].store(n, std::memory_order_relaxed);
+    }
+    return n;
+}
+
 struct Shape {
     int max_m, max_n, teams_per_block, threads;
     bool tile;   // a register tile (implements the convergence check)
+    int occ;     // waves per SIMD of kern
     void (*kern)(SinkArgs);
+    void (*kern_dense)(SinkArgs);   // the build for launches beyond occ waves per SIMD
 };
 
 template <int R, int C, int P, int Q, int W>
 constexpr Shape make_shape() {
-    return Shape{C * Q * W, R * P, (W == 1) ? 4 * (64 / (R * C)) : 4 / W, 256, true,
-                 &k_sink<R, C, P, Q, W>};
+    constexpr int occ = sink_occupancy<P, Q, W, false>();
+    constexpr int occ_dense = sink_occupancy<P, Q, W, true>();
+    return Shape{C * Q * W, R * P, (W == 1) ? 4 * (64 / (R * C)) : 4 / W, 256, true, occ,
+                 &k_sink<R, C, P, Q, W, occ>, &k_sink<R, C, P, Q, W, occ_dense>};
 }
 
 template <int MQ, int RP>
 constexpr Shape make_rows_shape() {
-    return Shape{MQ, 64 * RP, 1, 64, false, &k_sink_rows<MQ, RP>};
+    return Shape{MQ, 64 * RP, 1, 64, false, 0, &k_sink_rows<MQ, RP>, &k_sink_rows<MQ, RP>};
 }
 
 const Shape kShapes[] = {
@@ -1129,7 +1161,8 @@ hipError_t launch_sinkhorn(int shape, const SinkArgs& a, int max_m, int max_n, h
     // register tiles: each query's documents padded to whole blocks; the row
     // kernel has one team per block, so this is nitems for it
     const int64_t blocks = (int64_t)a.nq * ((a.d_end - a.d_begin + sh.teams_per_block - 1) / sh.teams_per_block);
-    return launch_kernel(sh.kern, dim3((unsigned)blocks), dim3(sh.threads), 0, s, a);
+    const bool dense = sh.occ > 0 && blocks * (sh.threads / 64) > (int64_t)sh.occ * 4 * device_cus();
+    return launch_kernel(dense ? sh.kern_dense : sh.kern, dim3((unsigned)blocks), dim3(sh.threads), 0, s, a);
 }
 
 }  // namespace wmd

@@ -166,6 +166,27 @@ def test_batch_equals_single_bitwise(ragged, wmd):
     assert rel_err(out[3], want).max() <= FP32_RTOL
 
 
+@pytest.mark.parametrize("tile", [2, 4])
+def test_dense_occupancy_build_equals_default_bitwise(wmd, tile):
+    """The 8-row, 8-column tiles have a second build at four waves per SIMD,
+    which a launch takes when it has more waves than three per SIMD: a batch
+    of 16 queries on 1200 documents (9600 waves) runs it, each query alone
+    (600 waves) the default build; the bits agree."""
+    vecs, ptr, ids, w = ragged_corpus(N=1200, seed=71, max_len=64)
+    rng = np.random.default_rng(72)
+    top = TILE_MAX_M[tile]
+    with wmd.Corpus(vecs, ptr, ids, w, device=0) as c:
+        queries = [(rng.choice(vecs.shape[0], m, replace=False).astype(np.int32),
+                    rng.geometric(0.5, m).astype(np.float32)) for m in rng.integers(top // 2 + 1, top + 1, 16)]
+        out, res = c.query_batch(queries, 10.0, 15, resid=True, tile=tile)
+        for b, (q, qw) in enumerate(queries):
+            one, r1 = c.query(q, qw, 10.0, 15, resid=True, tile=tile)
+            assert np.array_equal(out[b], one), b
+            assert np.array_equal(res[b], r1), b
+        want, _ = sinkhorn_wmd_sparse(vecs, queries[0][0], queries[0][1], ptr, ids, w, 10.0, 15)
+        assert rel_err(out[0], want).max() <= FP32_RTOL
+
+
 @pytest.mark.parametrize("bf16", [False, True])
 def test_shift_one_query_kernel_equals_batched_bitwise(wmd, bf16):
     """With the column shift, a single query of up to 64 words runs the
