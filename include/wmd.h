@@ -71,7 +71,7 @@ typedef struct wmd_query_options {
                                  launch; k > 0: at most k iterations per launch, x kept
                                  in device memory between launches */
     int32_t tile;             /* Sinkhorn launch shape: -1 picks by query length; 0..7
-                                 and 11..15 force that register tile, 8..10 that row-lane
+                                 and 11..16 force that register tile, 8..10 that row-lane
                                  tile (WMD_EINVAL when the query is
                                  longer than the tile holds); -2 uses the streaming
                                  kernel for every document.  Results are identical
@@ -84,7 +84,7 @@ typedef struct wmd_query_options {
                                  the row-marginal residual of the plan built from
                                  x(t-1)), else after `iters` updates.  The decision is
                                  taken in FP32.  Needs iters_per_launch = 0 and a tile
-                                 of -1, -2, 0..7 or 11..15. */
+                                 of -1, -2, 0..7 or 11..16. */
     int32_t lse;              /* nonzero: the same iteration carried in the log domain
                                  (Algorithm 1 on log u and log v, every product with K
                                  evaluated as a log-sum-exp over the same nonzeros, Sec. 4),

@@ -1116,14 +1116,18 @@ const Shape kShapes[] = {
     make_shape<8, 8, 8, 12, 1>(),    // 13: m <= 96,  one wave, 12 columns per lane
     make_shape<8, 8, 8, 12, 2>(),    // 14: m <= 192, two waves, 12 columns per lane
     make_shape<8, 8, 8, 12, 4>(),    // 15: m <= 384, four waves, 12 columns per lane
+    make_shape<8, 8, 8, 8, 4>(),     // 16: m <= 256, four waves
 };
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 // default shape per query-length class, smallest first: the first entry
 // whose max_m covers the query (measured on corpora of 5000 and 20000
-// documents of 10-60 words: the 12-column tiles run 33-48, 65-96, 129-192
-// and 257-384-word queries 13-21 % faster than the next power-of-two tile)
-const int kDefaultShapes[] = {8, 2, 12, 3, 13, 5, 14, 6, 15, 7};
-const int kAdaptiveShapes[] = {0, 2, 12, 3, 13, 5, 14, 6, 15, 7};  // register tiles only (convergence check)
+// documents of 10-60 words, one query and batches of 8-16: the 12-column
+// tiles run 33-48, 65-96, 129-192 and 257-384-word queries 13-21 % faster
+// than the next power-of-two tile; the 8 x 8 tiles at three or four waves per
+// SIMD run 49-64 and 193-256-word queries 2-15 % faster than the 16-row tiles
+// at two)
+const int kDefaultShapes[] = {8, 2, 12, 4, 13, 5, 14, 16, 15, 7};
+const int kAdaptiveShapes[] = {0, 2, 12, 4, 13, 5, 14, 16, 15, 7};  // register tiles only (convergence check)
 
 }  // namespace
 

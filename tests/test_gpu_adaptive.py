@@ -66,7 +66,7 @@ def test_adaptive_counts_and_distances(ragged, wmd, m, tile):
     np.testing.assert_allclose(res, wres, rtol=RESID_RTOL, atol=RESID_ATOL)
 
 
-@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, 6, 7, 11, 12, 13, 14, 15])   # the register tiles
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, 6, 7, 11, 12, 13, 14, 15, 16])   # the register tiles
 def test_adaptive_every_tile_shape(ragged, wmd, tile):
     # the stop decision sums rho over every lane of a team (each lane owns some
     # columns), across waves for the multi-wave shapes

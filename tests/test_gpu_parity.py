@@ -360,7 +360,7 @@ def test_c2_paper_shape_sampled(wmd):
     assert np.all(np.isfinite(got)) and np.all(got > 0)
 
 
-TILE_MAX_M = {0: 16, 1: 32, 2: 32, 3: 64, 4: 64, 5: 128, 6: 256, 7: 512, 8: 16, 9: 32, 10: 64, 11: 32, 12: 48, 13: 96, 14: 192, 15: 384}
+TILE_MAX_M = {0: 16, 1: 32, 2: 32, 3: 64, 4: 64, 5: 128, 6: 256, 7: 512, 8: 16, 9: 32, 10: 64, 11: 32, 12: 48, 13: 96, 14: 192, 15: 384, 16: 256}
 
 
 @pytest.mark.parametrize("tile", [-2] + sorted(TILE_MAX_M))
