@@ -445,6 +445,20 @@ __global__ __launch_bounds__(256) void k_dist_narrow(NarrowArgs a) {
         }
     };
     load_cols(0);
+    // the rows' epilogue metadata, loaded before the rows themselves: the
+    // barrier below waits for these loads (and, loads completing in order,
+    // for every load issued before them), not for the row stream
+    int e_word[4];
+    float e_norm[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t gi = rbase + 4 * lg + r;
+        const int64_t gc = (gi < a.U) ? gi : 0;
+        const int w = a.act_word[gc];
+        const float nv = a.norm[gc];
+        e_word[r] = (gi < a.U) ? w : -2;
+        e_norm[r] = (gi < a.U) ? nv : 0.f;
+    }
     uint4 fa[NC][2];
     {
         const int64_t row = rbase + lr;
@@ -459,17 +473,6 @@ __global__ __launch_bounds__(256) void k_dist_narrow(NarrowArgs a) {
             fa[c][0] = make_uint4(__float_as_uint(f0.x), __float_as_uint(f0.y), __float_as_uint(f0.z), __float_as_uint(f0.w));
             fa[c][1] = make_uint4(__float_as_uint(f1.x), __float_as_uint(f1.y), __float_as_uint(f1.z), __float_as_uint(f1.w));
         }
-    }
-    int e_word[4];
-    float e_norm[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int64_t gi = rbase + 4 * lg + r;
-        const int64_t gc = (gi < a.U) ? gi : 0;
-        const int w = a.act_word[gc];
-        const float nv = a.norm[gc];
-        e_word[r] = (gi < a.U) ? w : -2;
-        e_norm[r] = (gi < a.U) ? nv : 0.f;
     }
     store_cols();
     int qw[NP][2];
