@@ -129,6 +129,28 @@ __device__ __forceinline__ void epilogue(const DistArgs& a, const v4f (&acc)[RT]
         const int qw = (k < m) ? q->qid[k] : -1;
         const float lam = q->lambda, tau2 = q->tau2;
         const bool km = !q->km_from_k;
+        // squared distances (0 for a word the query shares); the FP32
+        // recompute below tau is rare, so it runs behind one wave-wide test
+        float d2v[RT][4];
+        bool need = false;
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const bool same = e_word[t][r] == qw;
+                d2v[t][r] = same ? 0.f : e_norm[t][r] + qnj - 2.f * acc[t][nb][r];
+                need |= k < m && !same && d2v[t][r] < tau2 && rbase + 16 * t + 4 * lg + r < a.U;
+            }
+        if (__builtin_amdgcn_ballot_w64(need)) {
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t gi = rbase + 16 * t + 4 * lg + r;
+                    if (k < m && e_word[t][r] != qw && d2v[t][r] < tau2 && gi < a.U)
+                        d2v[t][r] = direct_d2(a.act + gi * ldv, a.vecs + (int64_t)qw * ldv, ldv);
+                }
+        }
 #pragma unroll
         for (int t = 0; t < RT; ++t)
 #pragma unroll
@@ -141,14 +163,7 @@ __device__ __forceinline__ void epilogue(const DistArgs& a, const v4f (&acc)[RT]
                     if (km) q->KMt[gi * ldk + k] = 0.f;
                     continue;
                 }
-                float d;
-                if (e_word[t][r] == qw) {
-                    d = 0.f;
-                } else {
-                    float d2 = e_norm[t][r] + qnj - 2.f * acc[t][nb][r];
-                    if (d2 < tau2) d2 = direct_d2(a.act + gi * ldv, a.vecs + (int64_t)qw * ldv, ldv);
-                    d = sqrtf(fmaxf(d2, 0.f));
-                }
+                const float d = sqrtf(fmaxf(d2v[t][r], 0.f));
                 if (shift) {
                     *kt = d;
                     // d >= 0, so the bit patterns order like the values
@@ -550,6 +565,9 @@ __global__ __launch_bounds__(256) void k_dist_narrow(NarrowArgs a) {
     float dv[NP][2][4];
     bool live[NP][2][4];
     float dmin[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+    // squared distances (0 for a word the query shares); the FP32 recompute
+    // below tau is rare, so it runs behind one wave-wide test
+    bool need = false;
 #pragma unroll
     for (int ps = 0; ps < NP; ++ps)
 #pragma unroll
@@ -560,20 +578,33 @@ __global__ __launch_bounds__(256) void k_dist_narrow(NarrowArgs a) {
             for (int r = 0; r < 4; ++r) {
                 const int64_t gi = rbase + 4 * lg + r;
                 live[ps][nb][r] = k < m && gi < a.U;
-                float d = INFINITY;
-                if (live[ps][nb][r]) {
-                    if (e_word[r] == qw[ps][nb]) {
-                        d = 0.f;
-                    } else {
-                        float d2 = e_norm[r] + qnj - 2.f * acc[ps][nb][r];
-                        if (d2 < a.tau2) d2 = direct_d2(a.act + gi * ldv, a.vecs + (int64_t)qw[ps][nb] * ldv, ldv);
-                        d = sqrtf(fmaxf(d2, 0.f));
-                    }
+                const bool same = e_word[r] == qw[ps][nb];
+                dv[ps][nb][r] = same ? 0.f : e_norm[r] + qnj - 2.f * acc[ps][nb][r];
+                need |= live[ps][nb][r] && !same && dv[ps][nb][r] < a.tau2;
+            }
+        }
+    if (__builtin_amdgcn_ballot_w64(need)) {
+#pragma unroll
+        for (int ps = 0; ps < NP; ++ps)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t gi = rbase + 4 * lg + r;
+                    if (live[ps][nb][r] && e_word[r] != qw[ps][nb] && dv[ps][nb][r] < a.tau2)
+                        dv[ps][nb][r] = direct_d2(a.act + gi * ldv, a.vecs + (int64_t)qw[ps][nb] * ldv, ldv);
                 }
+    }
+#pragma unroll
+    for (int ps = 0; ps < NP; ++ps)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float d = live[ps][nb][r] ? sqrtf(fmaxf(dv[ps][nb][r], 0.f)) : INFINITY;
                 dv[ps][nb][r] = d;
                 dmin[r] = fminf(dmin[r], d);
             }
-        }
     if (a.shift) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
