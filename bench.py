@@ -40,6 +40,7 @@ only the 64-query batch calls (FP32 and BF16 distances), for counter runs.
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import multiprocessing as mp
@@ -81,6 +82,8 @@ def parse():
     p.add_argument("--queries-per-step", type=int, default=32,
                    help="queries of one step, each issued as its own call")
     p.add_argument("--workload", default="c2", choices=["c1", "c2"])
+    p.add_argument("--min-warmup-s", type=float, default=MIN_WARMUP_S,
+                   help="the warm-up runs --warmup steps and at least this many seconds")
     p.add_argument("--headline-streams", type=int, default=STREAMS,
                    help="streams the headline queries alternate over (1: every kernel runs alone, as the "
                         "single-stream kernel trace in profiles/ is taken)")
@@ -238,12 +241,12 @@ def cpu_baseline(wl, q, qw) -> dict:
 
 # ---------------------------------------------------------------- helpers
 
-def warm(step, steps: int):
-    """Run `steps` steps, then more until MIN_WARMUP_S has passed."""
+def warm(step, steps: int, min_s: float = MIN_WARMUP_S):
+    """Run `steps` steps, then more until `min_s` seconds have passed."""
     import torch
     t0 = time.perf_counter()
     i = 0
-    while i < steps or time.perf_counter() - t0 < MIN_WARMUP_S:
+    while i < steps or time.perf_counter() - t0 < min_s:
         step(i)
         i += 1
         if i % 256 == 0:
@@ -747,7 +750,12 @@ def main():
         for _ in range(qps_step):
             one(nstreams)
 
-    warmed = warm(step, args.warmup)
+    # no garbage-collector pause in the launching thread from here to the end
+    # of the timed region (collected first, so that no pause leaves the GPU
+    # idle between the warm-up and the timed steps)
+    gc.collect()
+    gc.disable()
+    warmed = warm(step, args.warmup, args.min_warmup_s)
 
     # timed region: K steps, no kernel timing inside it
     torch.cuda.synchronize()
@@ -756,6 +764,7 @@ def main():
         step(i)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    gc.enable()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = N * sp.iters * qps_step / (ms_per_step * 1e-3)
 
