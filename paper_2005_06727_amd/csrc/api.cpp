@@ -7,6 +7,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -661,6 +662,71 @@ static void corpus_free(wmd_corpus* c) {
     delete c;
 }
 
+// Documents of equal length are interchangeable for the kernels (a wave's rows
+// per lane depend on the lengths only, and every document's result on itself
+// only), so within each run of equal length the order puts documents that
+// share words on the same XCD.  A word's K row is fetched from memory once per
+// XCD whose L2 misses it, and the register-tile launch of a query (8
+// documents per block for the 17-48-word tiles) sends block b to XCD b mod 8:
+// sorted position p, counted from the first document of at most kTileMaxDoc
+// words, runs on XCD (p / 8) mod 8 (for every query of a batch alike, up to a
+// rotation).  Greedy: the documents of a run in order of their rarest word,
+// each to the XCD with positions left in the run that already holds most of
+// its words.  Longer documents (the streaming kernel) keep their order.
+static void cluster_by_xcd(std::vector<int32_t>& order, const std::vector<int32_t>& len,
+                           const std::vector<int64_t>& fptr, const std::vector<int32_t>& ids,
+                           const std::vector<int32_t>& remap, int64_t U) {
+    constexpr int kXcds = 8, kDocsPerBlock = 8;
+    const int64_t N = (int64_t)order.size();
+    int64_t p0 = 0;
+    while (p0 < N && len[order[p0]] > kTileMaxDoc) ++p0;
+    const int64_t d_tile = p0;
+    std::vector<int32_t> df((size_t)U, 0);
+    for (int32_t id : ids) ++df[remap[id]];
+    std::vector<uint8_t> on((size_t)U * kXcds, 0);   // on[w * 8 + x]: word w's row is on XCD x
+    auto xcd_of = [&](int64_t p) { return (int)(((p - d_tile) / kDocsPerBlock) % kXcds); };
+    std::vector<int32_t> run, key, bins[kXcds];
+    while (p0 < N) {
+        int64_t p1 = p0;
+        while (p1 < N && len[order[p1]] == len[order[p0]]) ++p1;
+        int quota[kXcds] = {0};
+        for (int64_t p = p0; p < p1; ++p) ++quota[xcd_of(p)];
+        run.assign(order.begin() + p0, order.begin() + p1);
+        key.assign(run.size(), 0);
+        for (size_t i = 0; i < run.size(); ++i) {
+            int32_t k = INT32_MAX;
+            for (int64_t e = fptr[run[i]]; e < fptr[run[i] + 1]; ++e) k = std::min(k, df[remap[ids[e]]]);
+            key[i] = k;
+        }
+        std::vector<size_t> idx(run.size());
+        for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+        std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return key[x] < key[y]; });
+        for (auto& b : bins) b.clear();
+        for (size_t i : idx) {
+            const int32_t j = run[i];
+            int best = -1;
+            int64_t best_new = INT64_MAX;
+            for (int x = 0; x < kXcds; ++x) {
+                if ((int)bins[x].size() >= quota[x]) continue;
+                int64_t fresh = 0;
+                for (int64_t e = fptr[j]; e < fptr[j + 1]; ++e) fresh += on[(size_t)remap[ids[e]] * kXcds + x] == 0;
+                if (fresh < best_new) {
+                    best_new = fresh;
+                    best = x;
+                }
+            }
+            bins[best].push_back(j);
+            for (int64_t e = fptr[j]; e < fptr[j + 1]; ++e) on[(size_t)remap[ids[e]] * kXcds + best] = 1;
+        }
+        size_t next[kXcds] = {0};
+        for (int64_t p = p0; p < p1; ++p) {
+            const int x = xcd_of(p);
+            order[p] = bins[x][next[x]++];
+        }
+        p0 = p1;
+    }
+}
+
 int wmd_corpus_create(const float* vecs, int64_t V, int32_t dim, const int64_t* doc_ptr,
                       const int32_t* word_ids, const float* weights, int64_t N,
                       const wmd_corpus_options* opt_in, wmd_corpus** out) {
@@ -717,10 +783,12 @@ int wmd_corpus_create(const float* vecs, int64_t V, int32_t dim, const int64_t* 
             act_word.push_back((int32_t)i);
         }
     const int64_t U = (int64_t)act_word.size();
-    // documents sorted by length, longest first (stable)
+    // documents sorted by length, longest first (stable), then within each
+    // run of equal length grouped by the XCD that will run them
     std::vector<int32_t> order((size_t)N);
     for (int64_t j = 0; j < N; ++j) order[j] = (int32_t)j;
     std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return len[x] > len[y]; });
+    cluster_by_xcd(order, len, fptr, ids, remap, U);
     std::vector<int32_t> sptr((size_t)N + 1, 0), scol((size_t)nnz), slen((size_t)N);
     std::vector<float> sw((size_t)nnz);
     for (int64_t d = 0; d < N; ++d) {

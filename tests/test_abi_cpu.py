@@ -84,3 +84,23 @@ def test_server_option_defaults_and_null_corpus():
         wmd.wmd_server_submit(None, [1], [1.0], 1.0, 1)
     assert e.value.code == wmd.WMD_EINVAL
     wmd.wmd_server_destroy(None)
+
+
+def test_valid_corpus_host_preparation_without_gpu():
+    """A valid ragged corpus passes the host-side preparation (validation,
+    vocabulary remap, the length sort and the grouping of equal-length
+    documents by XCD) and then stops at device selection when there is no
+    GPU: under the sanitizer build this runs that host code on the CPU."""
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present: the corpus would be created")
+    rng = np.random.default_rng(5)
+    V, N = 500, 300
+    vecs = rng.standard_normal((V, 8)).astype(np.float32)
+    lens = np.concatenate([np.arange(1, 101), rng.integers(1, 101, N - 100)])
+    ptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    ids = np.concatenate([rng.choice(V, n, replace=False) for n in lens]).astype(np.int32)
+    w = rng.random(ids.size).astype(np.float32) + 0.1
+    with pytest.raises(wmd.WmdError) as e:
+        wmd.wmd_corpus_create(vecs, ptr, ids, w, device=0)
+    assert e.value.code == wmd.WMD_EDEVICE
