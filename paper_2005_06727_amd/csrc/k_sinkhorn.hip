@@ -689,9 +689,10 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
 // rows per lane, 3 for 8 rows of up to 12 columns (12 columns spill a few
 // registers of the load phase to reach it, still faster than 2 waves), 2 for
 // 16 rows or 16 columns.  The multi-wave teams take what their registers allow
-// (the 12-column ones reach 3).  `dense`: a second build of the 8 x 8 tiles at
-// 4 waves (spilling a few registers), faster when the launch has more waves
-// than 3 per SIMD, slower for a single query on a small corpus.
+// (the 12-column ones reach 3).  `dense`: a second build of the one-wave tiles
+// with 8 rows and 8 columns per lane at 4 waves (spilling a few registers),
+// faster when the launch has more waves than 3 per SIMD, slower for a single
+// query on a small corpus.
 template <int P, int Q, int W, bool dense>
 constexpr int sink_occupancy() {
     if constexpr (W > 1) return 1;
