@@ -5,13 +5,13 @@
     python bench.py --lse
     python bench.py --profile-batch
 
-One step = a group of 32 queries (--queries-per-step), each issued as its own
+One step = a group of 128 queries (--queries-per-step), each issued as its own
 call and taken through the whole path (query preparation, distance GEMM + K
 epilogue, 15 fused Sinkhorn iterations + final WMD step) against the
 device-resident corpus, results written to device memory.  A group, not one
 query, so that the pipeline's fill and drain (the first distance kernel has
-nothing to overlap, the last Sinkhorn kernel neither) weigh the same in a
-20-step run as in a long one.  Workload: the
+nothing to overlap, the last Sinkhorn kernel neither) and any short stall
+weigh the same in a 20-step run (about 50 ms) as in a long one.  Workload: the
 paper-shaped single query (V=100000 words, 300-dim embeddings, N=5000
 documents of 10-60 distinct Zipf(1.1) words, one query of 20-40 words,
 lambda=10, 15 iterations), seeded synthetic data standing in for the paper's
@@ -79,7 +79,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=200)
     p.add_argument("--warmup", type=int, default=100)
-    p.add_argument("--queries-per-step", type=int, default=32,
+    p.add_argument("--queries-per-step", type=int, default=128,
                    help="queries of one step, each issued as its own call")
     p.add_argument("--workload", default="c2", choices=["c1", "c2"])
     p.add_argument("--min-warmup-s", type=float, default=MIN_WARMUP_S,
