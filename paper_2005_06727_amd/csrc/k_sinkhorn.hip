@@ -55,6 +55,16 @@ __device__ __forceinline__ float dpp(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
 }
 
+// v of lane k of this lane's quad (k a compile-time constant after unrolling)
+__device__ __forceinline__ float quad_bcast(float v, int k) {
+    switch (k) {
+        case 0: return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x00, 0xF, 0xF, true));
+        case 1: return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x55, 0xF, 0xF, true));
+        case 2: return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xAA, 0xF, 0xF, true));
+        default: return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xFF, 0xF, 0xF, true));
+    }
+}
+
 // lane ^ 16 and lane ^ 32 partner sums with the gfx950 row-swap VALU ops:
 // with both operands = v, the two results hold v of this lane and of its
 // partner, in the same order on both lanes, so both get identical bits.
@@ -501,11 +511,34 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
             }
             par ^= 1;
         }
+        if constexpr (C == 4 && W == 1) {
+            // The four lanes of a row group hold the same sums: lane b forms
+            // the reciprocals of rows b, b + 4, ... only, and each lane reads
+            // the others' with a quad broadcast (the same values, a quarter of
+            // the reciprocals)
+            // (the picks are bit masks: selects between array elements would
+            // be folded into an indexed access, i.e. scratch memory)
+            constexpr int K = (PN + 3) / 4;
+            const uint32_t m1 = 0u - (uint32_t)(b == 1), m2 = 0u - (uint32_t)(b == 2), m3 = 0u - (uint32_t)(b == 3);
+            float rq[K];
 #pragma unroll
-        for (int p = 0; p < PN; ++p) s[p] = rcp(s[p]);
-        __builtin_amdgcn_sched_barrier(0);
+            for (int j = 0; j < K; ++j) {
+                uint32_t x = __float_as_uint(s[4 * j]);
+                if (4 * j + 1 < PN) x = (__float_as_uint(s[4 * j + 1]) & m1) | (x & ~m1);
+                if (4 * j + 2 < PN) x = (__float_as_uint(s[4 * j + 2]) & m2) | (x & ~m2);
+                if (4 * j + 3 < PN) x = (__float_as_uint(s[4 * j + 3]) & m3) | (x & ~m3);
+                rq[j] = rcp(__uint_as_float(x));
+            }
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int p = 0; p < PN; ++p) v[p] = cval[p] * s[p];
+            for (int p = 0; p < PN; ++p) v[p] = cval[p] * quad_bcast(rq[p / 4], p % 4);
+        } else {
+#pragma unroll
+            for (int p = 0; p < PN; ++p) s[p] = rcp(s[p]);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int p = 0; p < PN; ++p) v[p] = cval[p] * s[p];
+        }
     };
 
     // y = A^T v summed over the team's rows (lanes a), the owned columns'
