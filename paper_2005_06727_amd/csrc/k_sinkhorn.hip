@@ -511,15 +511,18 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
             }
             par ^= 1;
         }
-        if constexpr (C == 4 && W == 1) {
-            // The four lanes of a row group hold the same sums: lane b forms
-            // the reciprocals of rows b, b + 4, ... only, and each lane reads
-            // the others' with a quad broadcast (the same values, a quarter of
-            // the reciprocals)
+        if constexpr (C <= 8) {
+            // Every lane of a row group (C lanes, whole quads) holds the same
+            // sums: lane b forms the reciprocals of rows p with p mod 4 = b
+            // mod 4 only, and each lane reads the others' with a quad
+            // broadcast (the same values, a quarter of the reciprocals; with
+            // C = 8 both quads of the group form their own copy).  The
+            // 16-row tiles (C = 16) measured no gain from it.
             // (the picks are bit masks: selects between array elements would
             // be folded into an indexed access, i.e. scratch memory)
             constexpr int K = (PN + 3) / 4;
-            const uint32_t m1 = 0u - (uint32_t)(b == 1), m2 = 0u - (uint32_t)(b == 2), m3 = 0u - (uint32_t)(b == 3);
+            const int bq = b & 3;
+            const uint32_t m1 = 0u - (uint32_t)(bq == 1), m2 = 0u - (uint32_t)(bq == 2), m3 = 0u - (uint32_t)(bq == 3);
             float rq[K];
 #pragma unroll
             for (int j = 0; j < K; ++j) {
@@ -721,14 +724,14 @@ __device__ __forceinline__ void sink_team(const SinkArgs& g, const QueryDev* qp,
 // Occupancy targets (waves per SIMD) of the one-wave register tiles: 5 for 4
 // rows per lane, 3 for 8 rows of up to 12 columns (12 columns spill a few
 // registers of the load phase to reach it, still faster than 2 waves), 2 for
-// 16 rows or 16 columns.  The multi-wave teams take what their registers allow
-// (the 12-column ones reach 3).  `dense`: a second build of the one-wave tiles
-// with 8 rows and 8 columns per lane at 4 waves (spilling a few registers),
-// faster when the launch has more waves than 3 per SIMD, slower for a single
-// query on a small corpus.
+// 16 rows or 16 columns.  The multi-wave teams with 8 rows of up to 12
+// columns per lane target 3 too; the others take what their registers allow.
+// `dense`: a second build of the one-wave tiles with 8 rows and 8 columns per
+// lane at 4 waves (spilling a few registers), faster when the launch has more
+// waves than 3 per SIMD, slower for a single query on a small corpus.
 template <int P, int Q, int W, bool dense>
 constexpr int sink_occupancy() {
-    if constexpr (W > 1) return 1;
+    if constexpr (W > 1) return (P <= 8 && Q <= 12) ? 3 : 1;
     else if constexpr (P >= 16 || Q > 12) return 2;
     else if constexpr (P <= 4) return 5;
     else if constexpr (dense && Q <= 8) return 4;
