@@ -420,12 +420,13 @@ __global__ __launch_bounds__(256) void k_dist_narrow(NarrowArgs a) {
 
     // Every load of the first pass is issued before the first wait, in three
     // dependent rounds: the query ids (kernel arguments), then the query
-    // column pieces and the corpus rows.  Columns beyond m and rows beyond U
-    // read the zero block (the address is chosen, not the value, so nothing is
-    // selected later).  Query columns -> LDS: 16-byte pieces, 32 columns x
-    // 8 NC pieces, NC per thread.
+    // column pieces and the corpus rows.  Rows beyond U read the zero block
+    // and columns beyond m the first query word's row (the address is chosen,
+    // not the value, so nothing is selected later).  Query columns -> LDS:
+    // 16-byte pieces, 32 columns x 8 NC pieces, NC per thread.
     const auto zero = gmem(a.zpad) + 4;
     uint4 v[NC];
+    const auto vecs = gmem(a.vecs);
     auto load_cols = [&](int ps) {
         int qrow[NC];
 #pragma unroll
@@ -436,8 +437,11 @@ __global__ __launch_bounds__(256) void k_dist_narrow(NarrowArgs a) {
 #pragma unroll
         for (int j = 0; j < NC; ++j) {
             const int p = tid + 256 * j;
-            const int cl = 32 * ps + p / (8 * NC), seg = p % (8 * NC);
-            const auto src = (cl < m) ? gmem(a.vecs) + (int64_t)qrow[j] * ldv : zero;
+            const int seg = p % (8 * NC);
+            // a column beyond m reads the first query word's row (qrow holds
+            // its id there): its products are never used (the epilogue
+            // writes 0 there), and the load needs no branch
+            const auto src = vecs + (int64_t)qrow[j] * ldv;
             if constexpr (BF16) {
                 const float4 f0 = ld4(src + seg * 8);
                 const float4 f1 = ld4(src + seg * 8 + 4);
