@@ -787,7 +787,10 @@ __global__ __launch_bounds__(256, OCC) void k_sink(SinkArgs g) {
     const int d = g.d_begin + (valid ? dd : 0);
     const QueryDev* qp = g.qd + qidx;
     take_iteration_range(g, qp);
-    const int m = valid ? qp->m : 0;
+    // the record's fields are read unconditionally (qp always points at a
+    // record of the launch), so no branch waits for them
+    const int qm = qp->m, qiters = qp->iters;
+    const int m = valid ? qm : 0;
     const int ldk = qp->ldk;
     // d is a document of the launch even for a team without one, so these
     // loads need no guard (a guarded load would be waited for inside its branch)
@@ -799,7 +802,7 @@ __global__ __launch_bounds__(256, OCC) void k_sink(SinkArgs g) {
     // Every team of a multi-wave block runs the query's iteration count (the
     // query is uniform over the block), a padding team too, so all waves run
     // the same barriers; a padding team stores nothing.
-    const int it_end = (valid || W > 1) ? min(g.it_begin + g.it_count, qp->iters) : g.it_begin;
+    const int it_end = (valid || W > 1) ? min(g.it_begin + g.it_count, qiters) : g.it_begin;
 
     // rows per lane for this wave: the most any of its teams needs (documents
     // of a launch are sorted by length, so the teams of a wave have similar n).
